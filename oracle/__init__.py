@@ -1,0 +1,29 @@
+"""FP64 CPU oracle for FFT-based angular-spectrum (ASM) propagation of a DOE.
+
+TEST INFRASTRUCTURE ONLY.  This package is the plain, slow, obviously correct
+definition that the HIP library is checked against.  Only the test suite, the
+smoke check in ``__graft_entry__`` and the CPU-baseline leg of ``bench.py`` may
+import it.  The product package never imports it, and it imports nothing from
+the product package: the two share no code.
+
+Parity status per function (see the module docstrings for the passages):
+
+* ``doe_field``, ``embed``, ``transfer_function``, ``propagate_padded``,
+  ``propagate``, ``psf``, ``psf_backward``: pinned (brute-force DFT on tiny
+  grids, Parseval, z = 0, +-z round trip, plane-wave eigenfunction,
+  sinc^2 / Airy lens focus, finite differences, adjoint dot product).
+"""
+
+from .asm import (  # noqa: F401
+    brute_propagate,
+    crop,
+    direct_dft2,
+    doe_field,
+    embed,
+    pad_offset,
+    propagate,
+    propagate_padded,
+    psf,
+    psf_backward,
+    transfer_function,
+)

@@ -1,0 +1,221 @@
+"""FP64 oracle of the DOE image-formation model (test infrastructure only).
+
+Only the test suite, the smoke check and the CPU-baseline leg of the benchmark
+may import this module; the product library never does.
+
+The model (paper Sec. 3.1, "Fabrication-aware Image Formation Model"):
+
+* Eq. (1): the DOE phase at wavelength lambda is
+  Phi = 2*pi/lambda * (n(lambda) - 1) * h.
+* Eq. (2): the field leaving the DOE is the incident field times exp(i*Phi).
+  Incident field here: a unit-amplitude normal plane wave, optionally
+  multiplied by a real aperture amplitude ``amp``.
+* Eq. (3): the field at distance z is F^-1{ F{E_doe} (.) H_lambda }.  The paper
+  does not write H; this oracle takes the plain angular-spectrum transfer
+  function of free space (Goodman) with the evanescent part cut off:
+  H = exp(i*2*pi*z*sqrt(1/lambda^2 - fx^2 - fy^2)) where
+  s = (lambda*fx)^2 + (lambda*fy)^2 < 1, and 0 elsewhere.
+* Eq. (4): the intensity |E_dest|^2 is summed over wavelengths.
+* The DOE (N x N samples) is zero-padded to an M x M grid, centred at offset
+  p0 = (M - N) // 2 (the paper's grids are twice the DOE extent, Table 2).
+
+Every array here is complex128 / float64.  ``scipy.fft`` is used as the FFT
+primitive; ``direct_dft2`` and ``brute_propagate`` are the independent
+definitions the FFT path is pinned against on tiny grids.
+
+The adjoint (``psf_backward``) follows from the paper's remark in Sec. 4.1
+that the DFT is a symmetric matrix, so the backward pass of a 2-D FFT is
+another 2-D FFT: the adjoint of ifft2 o diag(H) o fft2 is
+ifft2 o diag(conj H) o fft2.
+"""
+
+import os
+
+import numpy as np
+import scipy.fft as sfft
+
+# Threads handed to scipy.fft.  The CPU baseline reports this number.
+WORKERS = os.cpu_count() or 1
+
+
+def pad_offset(n, m):
+    """Offset of the N x N DOE inside the M x M grid (centred placement)."""
+    return (m - n) // 2
+
+
+def doe_field(h, lam, n_index, amp=None):
+    """Eq. (1)-(2): E = amp * exp(i * 2*pi/lam * (n - 1) * h), complex128."""
+    h = np.asarray(h, dtype=np.float64)
+    phi = (2.0 * np.pi / lam) * (n_index - 1.0) * h
+    e = np.exp(1j * phi)
+    if amp is not None:
+        e = e * np.asarray(amp, dtype=np.float64)
+    return e
+
+
+def embed(e, m):
+    """Zero-pad an N x N field into an M x M grid at offset p0 on both axes."""
+    n = e.shape[0]
+    p0 = pad_offset(n, m)
+    ep = np.zeros((m, m), dtype=np.complex128)
+    ep[p0:p0 + n, p0:p0 + n] = e
+    return ep
+
+
+def crop(u, n):
+    """The N x N window [p0, p0 + N)^2 of an M x M grid."""
+    p0 = pad_offset(n, u.shape[0])
+    return u[p0:p0 + n, p0:p0 + n]
+
+
+def transfer_function(m, dx, lam, z):
+    """Angular-spectrum transfer function on the FFT frequency grid (Eq. 3).
+
+    Frequencies are numpy's fftfreq (k / (M dx), k signed).  Rows index fy,
+    columns index fx.  A frequency propagates iff s < 1 with
+    s = (lam*fx)^2 + (lam*fy)^2, each square and the sum rounded once in FP64.
+    """
+    f = np.fft.fftfreq(m, d=dx)
+    a = lam * f
+    a2 = a * a
+    s = a2[:, None] + a2[None, :]
+    prop = s < 1.0
+    root = np.sqrt(np.where(prop, 1.0 - s, 0.0))
+    kz = 2.0 * np.pi * z / lam
+    return np.where(prop, np.exp(1j * (kz * root)), 0.0 + 0.0j)
+
+
+def propagate_padded(ep, dx, lam, z, adjoint=False):
+    """Eq. (3) on an already padded M x M field: ifft2(fft2(ep) * H).
+
+    ``adjoint=True`` applies the adjoint operator ifft2(fft2(ep) * conj(H)).
+    """
+    m = ep.shape[0]
+    h = transfer_function(m, dx, lam, z)
+    if adjoint:
+        h = np.conj(h)
+    a = sfft.fft2(ep, workers=WORKERS)
+    return sfft.ifft2(a * h, workers=WORKERS)
+
+
+def propagate(u_in, m, dx, lam, z, out_mode="crop", adjoint=False):
+    """Propagate an N x N complex field (zero-padded to M x M) by z.
+
+    Returns the N x N crop at [p0, p0+N)^2 (``out_mode="crop"``) or the whole
+    M x M plane (``out_mode="full"``).
+    """
+    u_in = np.asarray(u_in, dtype=np.complex128)
+    n = u_in.shape[0]
+    u = propagate_padded(embed(u_in, m), dx, lam, z, adjoint=adjoint)
+    return crop(u, n) if out_mode == "crop" else u
+
+
+def psf(h, dx, z, m, lams, n_index, weights=None, amp=None, out_mode="crop",
+        return_fields=False):
+    """Eq. (4): sum_k w_k |E_dest,k|^2 over the wavelengths, in k order.
+
+    Returns the float64 PSF (N x N crop or M x M full).  With
+    ``return_fields=True`` also returns the list of complex128 fields U_k
+    (same region as the PSF).
+    """
+    h = np.asarray(h, dtype=np.float64)
+    n = h.shape[0]
+    k_count = len(lams)
+    if weights is None:
+        weights = np.ones(k_count)
+    shape = (n, n) if out_mode == "crop" else (m, m)
+    acc = np.zeros(shape, dtype=np.float64)
+    fields = []
+    for k in range(k_count):
+        e = doe_field(h, lams[k], n_index[k], amp)
+        u = propagate(e, m, dx, lams[k], z, out_mode=out_mode)
+        acc += float(weights[k]) * (u.real * u.real + u.imag * u.imag)
+        if return_fields:
+            fields.append(u)
+    return (acc, fields) if return_fields else acc
+
+
+def psf_backward(h, dx, z, m, lams, n_index, grad_psf, weights=None, amp=None,
+                 out_mode="crop"):
+    """Gradient dL/dh of a real loss L given G = dL/dPSF (same region as the PSF).
+
+    Convention: the gradient of L with respect to a complex field u is
+    g = dL/dRe(u) + i dL/dIm(u).  Per wavelength k:
+      g_U  = 2 w_k G * U_k
+      g_Ep = ifft2(fft2(g_U embedded) * conj(H_k))       (adjoint of Eq. 3)
+      dL/dh += c_k * Im(g_E * conj(E_k)),  c_k = 2*pi*(n_k - 1)/lam_k
+    where g_E is g_Ep on the DOE window and E_k is Eq. (2).
+    """
+    h = np.asarray(h, dtype=np.float64)
+    g = np.asarray(grad_psf, dtype=np.float64)
+    n = h.shape[0]
+    k_count = len(lams)
+    if weights is None:
+        weights = np.ones(k_count)
+    grad = np.zeros((n, n), dtype=np.float64)
+    for k in range(k_count):
+        e = doe_field(h, lams[k], n_index[k], amp)
+        ep = embed(e, m)
+        u = propagate_padded(ep, dx, lams[k], z)
+        if out_mode == "crop":
+            g_u = embed(2.0 * float(weights[k]) * g * crop(u, n), m)
+        else:
+            g_u = 2.0 * float(weights[k]) * g * u
+        g_ep = propagate_padded(g_u, dx, lams[k], z, adjoint=True)
+        g_e = crop(g_ep, n)
+        c_k = 2.0 * np.pi * (n_index[k] - 1.0) / lams[k]
+        grad += c_k * np.imag(g_e * np.conj(e))
+    return grad
+
+
+# ---------------------------------------------------------------------------
+# Independent definitions used to pin the FFT path on tiny grids.
+# ---------------------------------------------------------------------------
+
+def direct_dft2(x, inverse=False):
+    """2-D DFT written as the matrix product W x W^T (no FFT).
+
+    Forward: X[u, v] = sum_{y, x} x[y, x] exp(-2 pi i (u y + v x) / M).
+    Inverse: the conjugate kernel and a 1/M^2 factor.
+    """
+    x = np.asarray(x, dtype=np.complex128)
+    m = x.shape[0]
+    idx = np.arange(m)
+    sign = 1.0 if inverse else -1.0
+    w = np.exp(sign * 2j * np.pi * np.outer(idx, idx) / m)
+    out = w @ x @ w.T
+    return out / (m * m) if inverse else out
+
+
+def _signed_freq(k, m, dx):
+    """Frequency of DFT bin k on an M-point grid of pitch dx: k/(M dx) for
+    k < M/2, (k - M)/(M dx) otherwise."""
+    ks = k if k < (m + 1) // 2 else k - m
+    return ks / (m * dx)
+
+
+def brute_propagate(u_in, m, dx, lam, z):
+    """Eq. (3) by explicit sums over the M x M grid (tiny M only).
+
+    Every bin's transfer value is evaluated on its own from the physical
+    frequency, the spectrum and its inverse are plain double sums.  Returns the
+    full M x M field for a centred N x N input.
+    """
+    ep = embed(np.asarray(u_in, dtype=np.complex128), m)
+    idx = np.arange(m)
+    u_out = np.zeros((m, m), dtype=np.complex128)
+    for fu in range(m):
+        fy = _signed_freq(fu, m, dx)
+        for fv in range(m):
+            fx = _signed_freq(fv, m, dx)
+            s = (lam * fx) * (lam * fx) + (lam * fy) * (lam * fy)
+            if not s < 1.0:
+                continue
+            hval = np.exp(1j * 2.0 * np.pi * z * np.sqrt(1.0 / (lam * lam) - fx * fx - fy * fy))
+            # forward DFT coefficient of bin (fu, fv)
+            ky = np.exp(-2j * np.pi * fu * idx / m)
+            kx = np.exp(-2j * np.pi * fv * idx / m)
+            coef = ky @ ep @ kx
+            # add this bin's plane wave to the output
+            u_out += (coef * hval / (m * m)) * np.outer(np.conj(ky), np.conj(kx))
+    return u_out

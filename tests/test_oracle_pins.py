@@ -1,0 +1,266 @@
+"""Pins of the FP64 oracle against facts fixed outside it (CPU only).
+
+Each test checks the oracle against something it does not compute itself: a
+direct DFT, an explicit per-bin sum, Parseval's theorem, the free-space
+plane-wave eigenfunction, closed-form focal spots of an ideal lens (Goodman,
+Introduction to Fourier Optics: sinc^2 for a square and Airy for a circular
+pupil), invariances of Eq. (1)-(2), finite differences and the adjoint
+identity.
+"""
+
+import numpy as np
+import pytest
+import scipy.special as sps
+
+import oracle
+from oracle import asm
+from paper_2505_22313_amd import workloads as wl
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def rand_field(rng, n):
+    return rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+
+
+# ---------------------------------------------------------------------------
+# FFT primitive and transfer function against direct sums
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m", [8, 16, 32, 64])
+def test_fft_path_matches_direct_dft(m):
+    """Eq. (3) through scipy.fft equals Eq. (3) through the matrix DFT."""
+    rng = np.random.default_rng(m)
+    ep = rand_field(rng, m)
+    dx, lam, z = 0.3, 0.5, 7.0
+    h = oracle.transfer_function(m, dx, lam, z)
+    want = asm.direct_dft2(asm.direct_dft2(ep) * h, inverse=True)
+    got = oracle.propagate_padded(ep, dx, lam, z)
+    assert rel(got, want) < 1e-12
+
+
+def _mask_margin(m, dx, lam):
+    f = np.fft.fftfreq(m, d=dx)
+    s = (lam * f)[:, None] ** 2 + (lam * f)[None, :] ** 2
+    return float(np.min(np.abs(s - 1.0)))
+
+
+@pytest.mark.parametrize("m,n,dx,lam,z", [
+    (8, 5, 0.3, 0.5, 3.0),      # evanescent corners present
+    (16, 8, 0.3, 0.5, 11.0),
+    (16, 16, 1.0, 0.55, 40.0),  # all bins propagate, no padding
+    (12, 7, 0.27, 0.5, 5.0),    # even, non power of two
+])
+def test_propagate_matches_brute_force(m, n, dx, lam, z):
+    """Oracle propagate == per-bin explicit sum with an independently evaluated
+    transfer value and evanescent test."""
+    assert _mask_margin(m, dx, lam) > 1e-6  # no bin sits on the cutoff
+    rng = np.random.default_rng(100 + m + n)
+    u = rand_field(rng, n)
+    got = oracle.propagate(u, m, dx, lam, z, out_mode="full")
+    want = asm.brute_propagate(u, m, dx, lam, z)
+    assert rel(got, want) < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# Energy, identities, invariances
+# ---------------------------------------------------------------------------
+
+def test_parseval_all_bins_propagate():
+    """Unit-modulus DOE, every bin propagating: sum |U|^2 over the full plane
+    equals N^2 (the transfer function is unimodular)."""
+    n, m, dx, lam, z = 96, 192, 1.0, 0.55, 5000.0
+    h = wl.uniform_heights(n, seed=11)
+    p = oracle.psf(h, dx, z, m, [lam], [1.46], out_mode="full")
+    assert abs(p.sum() / n ** 2 - 1.0) < 1e-12
+
+
+def test_evanescent_energy_loss():
+    """With pitch 0.25 um at 520.6 nm (the paper's hologram wavelength) the
+    axis bins beyond |f| = 1/lambda are cut: the output energy equals the
+    spectral energy of the propagating bins (explicit per-bin test)."""
+    n, m, dx, lam, z = 16, 32, 0.25, 0.5206, 30.0
+    rng = np.random.default_rng(7)
+    e = np.exp(1j * rng.uniform(0, 2 * np.pi, (n, n)))
+    u = oracle.propagate(e, m, dx, lam, z, out_mode="full")
+    spec = asm.direct_dft2(oracle.embed(e, m))
+    keep = 0.0
+    for fu in range(m):
+        for fv in range(m):
+            fy = asm._signed_freq(fu, m, dx)
+            fx = asm._signed_freq(fv, m, dx)
+            if (lam * fx) ** 2 + (lam * fy) ** 2 < 1.0:
+                keep += abs(spec[fu, fv]) ** 2
+    energy = float(np.sum(np.abs(u) ** 2))
+    assert abs(energy - keep / m ** 2) / energy < 1e-12
+    assert energy < n * n * (1 - 1e-3)
+
+
+def test_z_zero_is_identity():
+    n, m, dx, lam = 40, 64, 1.0, 0.55
+    rng = np.random.default_rng(3)
+    u = rand_field(rng, n)
+    out = oracle.propagate(u, m, dx, lam, 0.0, out_mode="full")
+    assert rel(out, oracle.embed(u, m)) < 1e-14
+
+
+def test_plus_minus_z_round_trip():
+    n, m, dx, lam, z = 40, 64, 1.0, 0.55, 3000.0
+    rng = np.random.default_rng(4)
+    u = rand_field(rng, n)
+    fwd = oracle.propagate(u, m, dx, lam, z, out_mode="full")
+    back = oracle.propagate_padded(fwd, dx, lam, -z)
+    assert rel(back, oracle.embed(u, m)) < 1e-12
+
+
+def test_constant_height_only_shifts_phase():
+    n, m, dx, lam, nn, z = 48, 96, 1.0, 0.55, 1.46, 2000.0
+    h = wl.uniform_heights(n, seed=5).astype(np.float64)
+    a = oracle.psf(h, dx, z, m, [lam], [nn])
+    b = oracle.psf(h + 0.37, dx, z, m, [lam], [nn])
+    assert rel(b, a) < 1e-12
+
+
+def test_one_wave_height_is_invisible():
+    """Adding lambda/(n-1) to h adds exactly 2 pi to the phase of Eq. (1)."""
+    n, m, dx, lam, nn, z = 48, 96, 1.0, 0.55, 1.46, 2000.0
+    h = wl.uniform_heights(n, seed=6).astype(np.float64)
+    e0 = oracle.doe_field(h, lam, nn)
+    e1 = oracle.doe_field(h + lam / (nn - 1.0), lam, nn)
+    assert rel(e1, e0) < 1e-13
+    u0 = oracle.propagate(e0, m, dx, lam, z)
+    u1 = oracle.propagate(e1, m, dx, lam, z)
+    assert rel(u1, u0) < 1e-12
+
+
+def test_wavelength_sum_is_linear():
+    n, m, dx, z = 48, 96, 1.0, 2000.0
+    lams = [0.45, 0.55, 0.65]
+    nidx = wl.cauchy_index(lams)
+    w = [0.5, 1.0, 2.0]
+    h = wl.uniform_heights(n, seed=8)
+    tot = oracle.psf(h, dx, z, m, lams, nidx, weights=w)
+    parts = sum(w[k] * oracle.psf(h, dx, z, m, [lams[k]], [nidx[k]]) for k in range(3))
+    assert rel(tot, parts) < 1e-13
+
+
+@pytest.mark.parametrize("u0,v0", [(0, 3), (5, -7), (-20, 11), (31, 31)])
+def test_plane_wave_eigenfunction(u0, v0):
+    """A plane wave exp(2 pi i (fx x + fy y)) travels by exp(i 2 pi z cos(theta)
+    / lambda) with cos(theta) = sqrt(1 - (lambda fx)^2 - (lambda fy)^2); an
+    evanescent one is cut (Goodman, free-space transfer function)."""
+    m, dx, lam, z = 64, 0.4, 0.6, 123.0
+    yy, xx = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
+    wave = np.exp(2j * np.pi * (u0 * yy + v0 * xx) / m)
+    out = oracle.propagate(wave, m, dx, lam, z, out_mode="full")
+    fy, fx = u0 / (m * dx), v0 / (m * dx)
+    cos2 = 1.0 - (lam * fx) ** 2 - (lam * fy) ** 2
+    if cos2 > 0:
+        want = np.exp(1j * 2 * np.pi * z * np.sqrt(cos2) / lam) * wave
+        assert rel(out, want) < 1e-12
+    else:
+        assert np.max(np.abs(out)) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Closed-form focal spots of an ideal lens
+# ---------------------------------------------------------------------------
+
+def _lens_psf(amp, n, m, dx, lam, f, nn=1.5):
+    h = wl.ideal_lens_heights(n, dx, f, lam, nn).astype(np.float64)
+    return oracle.psf(h, dx, f, m, [lam], [nn], amp=amp)
+
+
+def test_square_lens_focus_sinc2():
+    """Square pupil of side L focused at f: I(x, 0) = (L^2/(lam f))^2
+    sinc^2(L x/(lam f)) (Fraunhofer pattern at the focal plane)."""
+    n, m, dx, lam, f = 512, 1024, 1.0, 0.55, 5000.0
+    p = _lens_psf(None, n, m, dx, lam, f)
+    c = n // 2
+    side = n * dx
+    i0 = (side * side / (lam * f)) ** 2
+    assert abs(p[c, c] / i0 - 1.0) < 0.02
+    assert np.unravel_index(np.argmax(p), p.shape) == (c, c)
+    x = np.arange(-12, 13) * dx
+    want = i0 * np.sinc(side * x / (lam * f)) ** 2
+    assert np.max(np.abs(p[c, c - 12:c + 13] - want)) / i0 < 0.02
+    assert np.max(np.abs(p[c - 12:c + 13, c] - want)) / i0 < 0.02
+
+
+def test_circular_lens_focus_airy():
+    """Circular pupil radius R: Airy pattern I0 [2 J1(v)/v]^2,
+    v = 2 pi R rho/(lam f), I0 = (pi R^2/(lam f))^2; 83.8 % of the power lies
+    inside the first dark ring (rho = 0.61 lam f / R)."""
+    n, m, dx, lam, f, rad = 512, 1024, 1.0, 0.55, 5000.0, 200.0
+    amp = wl.circular_aperture(n, dx, rad)
+    p = _lens_psf(amp, n, m, dx, lam, f)
+    c = n // 2
+    i0 = (np.pi * rad * rad / (lam * f)) ** 2
+    assert abs(p[c, c] / i0 - 1.0) < 0.02
+    x = np.arange(1, 20) * dx
+    v = 2 * np.pi * rad * x / (lam * f)
+    want = i0 * (2 * sps.j1(v) / v) ** 2
+    assert np.max(np.abs(p[c, c + 1:c + 20] - want)) / i0 < 0.02
+    yy, xx = np.meshgrid(np.arange(n) - c, np.arange(n) - c, indexing="ij")
+    r_dark = 0.61 * lam * f / rad / dx
+    inside = p[(yy ** 2 + xx ** 2) <= r_dark ** 2].sum()
+    total = float(amp.astype(np.float64).sum())  # input power (Parseval)
+    assert abs(inside / total - 0.838) < 0.02
+
+
+# ---------------------------------------------------------------------------
+# Gradient
+# ---------------------------------------------------------------------------
+
+def _loss_setup(out_mode):
+    n, m, dx, z = 32, 64, 1.0, 1500.0
+    lams = np.array([0.45, 0.55, 0.65])
+    nidx = wl.cauchy_index(lams)
+    w = np.array([1.0, 0.7, 1.3])
+    rng = np.random.default_rng(21)
+    h = rng.uniform(0, 1.2, (n, n))
+    amp = rng.uniform(0.5, 1.0, (n, n))
+    shape = (n, n) if out_mode == "crop" else (m, m)
+    target = rng.uniform(0, 2.0, shape)
+
+    def loss(hh):
+        p = oracle.psf(hh, dx, z, m, lams, nidx, weights=w, amp=amp, out_mode=out_mode)
+        return float(np.mean((p - target) ** 2))
+
+    def grad(hh):
+        p = oracle.psf(hh, dx, z, m, lams, nidx, weights=w, amp=amp, out_mode=out_mode)
+        g = 2.0 * (p - target) / p.size
+        return oracle.psf_backward(hh, dx, z, m, lams, nidx, g, weights=w, amp=amp,
+                                   out_mode=out_mode)
+
+    return h, loss, grad, rng
+
+
+@pytest.mark.parametrize("out_mode", ["crop", "full"])
+def test_gradient_finite_differences(out_mode):
+    h, loss, grad, rng = _loss_setup(out_mode)
+    g = grad(h)
+    eps = 1e-5
+    d = rng.standard_normal(h.shape)
+    fd = (loss(h + eps * d) - loss(h - eps * d)) / (2 * eps)
+    assert abs(fd - np.sum(g * d)) / abs(fd) < 1e-7
+    for _ in range(4):
+        i, j = rng.integers(0, h.shape[0], 2)
+        e = np.zeros_like(h)
+        e[i, j] = 1.0
+        fd = (loss(h + eps * e) - loss(h - eps * e)) / (2 * eps)
+        assert abs(fd - g[i, j]) <= 1e-6 * np.max(np.abs(g)) + 1e-8 * abs(fd)
+
+
+def test_adjoint_dot_product():
+    """<P x, y> == <x, P^H y> for the padded propagation operator."""
+    m, dx, lam, z = 64, 0.3, 0.5, 50.0
+    rng = np.random.default_rng(9)
+    x, y = rand_field(rng, m), rand_field(rng, m)
+    px = oracle.propagate_padded(x, dx, lam, z)
+    phy = oracle.propagate_padded(y, dx, lam, z, adjoint=True)
+    lhs = np.vdot(y, px)
+    rhs = np.vdot(phy, x)
+    assert abs(lhs - rhs) / abs(lhs) < 1e-12

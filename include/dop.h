@@ -1,0 +1,222 @@
+/*
+ * dop.h - C ABI of libdop, an MI355X (gfx950) engine for FFT-based
+ * angular-spectrum propagation of large diffractive optical elements.
+ *
+ * What is computed (Wei et al., "Large-Area Fabrication-Aware Computational
+ * Diffractive Optics", ACM TOG 2025, Sec. 3.1):
+ *   Eq. (1)  Phi_k(x,y) = 2 pi / lambda_k * (n_k - 1) * h(x,y)
+ *   Eq. (2)  E_k = amp * exp(i Phi_k)        (normal plane wave times an
+ *                                              optional real aperture)
+ *   Eq. (3)  U_k = F^-1{ F{E_k padded} * H_k }
+ *            H_k(fx,fy) = exp(i 2 pi z sqrt(1/lambda_k^2 - fx^2 - fy^2))
+ *                         when s = (lambda_k fx)^2 + (lambda_k fy)^2 < 1,
+ *                         0 otherwise (evanescent cutoff)
+ *   Eq. (4)  PSF = sum_k w_k |U_k|^2            (fixed k order)
+ * The N x N DOE is zero-padded into an M x M grid at offset
+ * p0 = (M - N) / 2 (integer division) on both axes; frequencies are
+ * f = k_signed / (M dx) with k_signed = k for k < M/2, k - M otherwise.
+ * The backward pass uses the adjoint of Eq. (3), which the paper notes is
+ * again a 2-D FFT chain (Sec. 4.1): the same passes with conj(H).
+ *
+ * Conventions common to every entry point:
+ *  - Lengths (dx, z, lambda) share one unit of the caller's choosing.
+ *  - Device arrays are row-major, x fastest, caller-owned, and must stay
+ *    alive until the work enqueued on `stream` has completed.  Complex
+ *    arrays are interleaved float pairs (re, im) ("c64").
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls
+ *    enqueue work and return without synchronising.
+ *  - Every argument is validated before anything is enqueued.  On any error
+ *    nothing is launched and no output is touched; the return value says
+ *    why and dop_last_error() (thread-local) gives the detail.
+ *  - Results are deterministic: no floating-point atomics, fixed wavelength
+ *    order, so the same inputs give bitwise-identical outputs.
+ *  - A context may be used from several host threads at once on different
+ *    streams, provided each call has its own workspace.
+ */
+#ifndef DOP_H_
+#define DOP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DOP_OK = 0,
+  DOP_NOT_READY = 1,            /* serve: ticket still queued or running   */
+  DOP_ERR_INVALID_ARG = -1,     /* malformed argument                      */
+  DOP_ERR_UNSUPPORTED = -2,     /* valid but not supported (e.g. M not a
+                                   power of two, M > 65536)                 */
+  DOP_ERR_WORKSPACE = -3,       /* workspace missing or too small          */
+  DOP_ERR_DEVICE = -4,          /* HIP runtime or launch failure           */
+  DOP_ERR_BUDGET = -5,          /* serve: request can never fit the arena  */
+  DOP_ERR_NOT_FOUND = -6,       /* serve: unknown ticket                   */
+  DOP_ERR_SHUTDOWN = -7,        /* serve: server is shutting down          */
+  DOP_ERR_TIMEOUT = -8          /* serve: wait timed out                   */
+} dop_status;
+
+/* Output region of a field or PSF. */
+enum {
+  DOP_OUT_CROP = 0,  /* N x N window [p0, p0+N)^2 of the propagated plane  */
+  DOP_OUT_FULL = 1   /* the whole M x M plane, in centred coordinates      */
+};
+
+/* Operation selector for dop_workspace_size. */
+enum { DOP_OP_PROPAGATE = 0, DOP_OP_PSF = 1, DOP_OP_PSF_BACKWARD = 2 };
+
+/* Limits. */
+#define DOP_MAX_M 65536
+#define DOP_MIN_M 16
+#define DOP_MAX_LAMBDA 64
+
+/*
+ * Problem description (paper Sec. 3.1: grid, pitch, wavelengths, index,
+ * distance, padding).  Host arrays are read during the call only.
+ */
+typedef struct {
+  int32_t n;             /* DOE grid n x n, 1 <= n <= m                       */
+  int32_t m;             /* padded FFT grid m x m: power of two, 16..65536    */
+  double dx;             /* sampling pitch (> 0)                              */
+  double z;              /* propagation distance (any sign, 0 allowed)        */
+  int32_t n_lambda;      /* K, 1..DOP_MAX_LAMBDA                              */
+  const double *lambda;  /* host[K], > 0, same unit as dx                     */
+  const double *n_index; /* host[K], refractive index n(lambda_k), finite     */
+  const float *weight;   /* host[K] PSF weights w_k, or NULL for all 1        */
+  int32_t out_mode;      /* DOP_OUT_CROP or DOP_OUT_FULL                      */
+  int32_t flags;         /* must be 0                                         */
+} dop_problem;
+
+typedef struct dop_context dop_context;
+typedef struct dop_server dop_server;
+
+/* Human-readable name of a status code (static string). */
+const char *dop_status_string(dop_status s);
+
+/* Detail of the last error raised on the calling thread ("" if none). */
+const char *dop_last_error(void);
+
+/*
+ * Create a context on HIP device `device`: uploads the twiddle table
+ * (exp(-2 pi i j / 65536), generated in FP64 and rounded to c64, 512 KiB).
+ * The context owns only that table.  Synchronous.
+ */
+dop_status dop_context_create(int device, dop_context **out);
+dop_status dop_context_destroy(dop_context *ctx);
+
+/*
+ * Workspace bytes an operation needs for `prob` (op = DOP_OP_*): one M x M
+ * c64 field (8 M^2 bytes).  Pure host call.
+ */
+dop_status dop_workspace_size(const dop_context *ctx, const dop_problem *prob,
+                              int op, size_t *bytes);
+
+/*
+ * Eq. (3) for one wavelength index k (0 <= k < K; lambda[k] is used, n_index
+ * and weight are ignored): propagates the N x N c64 field `u_in` (zero-padded
+ * to M x M at p0) by z.  `u_out` receives N x N c64 (CROP) or M x M c64
+ * (FULL, centred coordinates).  `u_in` and `u_out` must not overlap.
+ */
+dop_status dop_propagate(dop_context *ctx, const dop_problem *prob, int k,
+                         const void *u_in, void *u_out, void *ws,
+                         size_t ws_bytes, void *stream);
+
+/*
+ * Eq. (1)-(4): PSF = sum_k w_k |U_k|^2 for height map `h` (N x N float32)
+ * and optional aperture `amp` (N x N float32, NULL = 1).  `psf` is
+ * overwritten: N x N float32 (CROP) or M x M float32 (FULL).  If `saved_u`
+ * is not NULL (CROP only) it receives the fields U_k as K x N x N c64, the
+ * state dop_psf_backward needs.
+ */
+dop_status dop_psf(dop_context *ctx, const dop_problem *prob, const float *h,
+                   const float *amp, float *psf, void *saved_u, void *ws,
+                   size_t ws_bytes, void *stream);
+
+/*
+ * Gradient of a real loss L with respect to h, given grad_psf = dL/dPSF
+ * (N x N float32, CROP only) and the fields saved by dop_psf (K x N x N c64).
+ * Per wavelength: g_U = 2 w_k G U_k, g_E = adjoint of Eq. (3) applied to g_U
+ * (conj(H_k)), dL/dh += c_k Im(g_E conj(E_k)) with c_k = 2 pi (n_k - 1) /
+ * lambda_k and E_k recomputed from h and amp.  `grad_h` (N x N float32) is
+ * overwritten.
+ */
+dop_status dop_psf_backward(dop_context *ctx, const dop_problem *prob,
+                            const float *h, const float *amp,
+                            const void *saved_u, const float *grad_psf,
+                            float *grad_h, void *ws, size_t ws_bytes,
+                            void *stream);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of PSF requests (dop_psf, CROP or FULL) of
+ * mixed sizes and wavelength counts.  The server sub-allocates workspaces
+ * from a caller-provided device arena (it never calls hipMalloc per request),
+ * admits queued requests in FIFO order as slots and arena memory free up, and
+ * runs each admitted request on its own stream so that their passes overlap
+ * on the GPU.  Thread-safe.
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+  uint64_t submitted;     /* requests accepted by dop_serve_submit           */
+  uint64_t completed;     /* requests finished (ok or failed)                */
+  uint64_t failed;        /* requests that finished with an error            */
+  uint32_t queued;        /* waiting for admission                           */
+  uint32_t running;       /* admitted and not yet finished                   */
+  uint64_t arena_bytes;   /* arena size                                      */
+  uint64_t arena_peak;    /* peak bytes sub-allocated                        */
+  double p50_ms;          /* latency (submit -> done) percentiles over all   */
+  double p99_ms;          /*   completed requests                            */
+  double mean_ms;
+} dop_serve_stats;
+
+/*
+ * Create a server on `ctx` with `max_slots` (1..64) concurrent requests,
+ * sub-allocating from `arena` (device memory, `arena_bytes`, caller-owned,
+ * alive until dop_serve_destroy returns).  Starts one scheduler thread.
+ */
+dop_status dop_serve_create(dop_context *ctx, void *arena, size_t arena_bytes,
+                            int max_slots, dop_server **out);
+
+/*
+ * Queue a PSF request.  `prob` and its host arrays are copied.  `h` (N x N
+ * float32), `amp` (N x N float32 or NULL) and `psf` (output, as dop_psf)
+ * are device buffers that must stay alive until the ticket completes.
+ * DOP_ERR_BUDGET if the request could never fit the arena.
+ */
+dop_status dop_serve_submit(dop_server *srv, const dop_problem *prob,
+                            const float *h, const float *amp, float *psf,
+                            uint64_t *ticket);
+
+/* DOP_OK when done, DOP_NOT_READY while queued/running, or the request's
+ * error.  A finished ticket can be polled any number of times. */
+dop_status dop_serve_poll(dop_server *srv, uint64_t ticket);
+
+/* Block until the ticket is done (DOP_OK or its error) or `timeout_s`
+ * (< 0: forever) elapses (DOP_ERR_TIMEOUT). */
+dop_status dop_serve_wait(dop_server *srv, uint64_t ticket, double timeout_s);
+
+/* Latency (ms, submit -> done) of a finished ticket. */
+dop_status dop_serve_latency(dop_server *srv, uint64_t ticket, double *ms);
+
+dop_status dop_serve_stats_get(dop_server *srv, dop_serve_stats *out);
+
+/* Stop admitting, cancel queued requests (DOP_ERR_SHUTDOWN), wait for
+ * running ones, free everything. */
+dop_status dop_serve_destroy(dop_server *srv);
+
+/*
+ * Test hook: a server whose executor is a host-side mock instead of the GPU.
+ * Each admitted request "runs" for service_us_per_mpix * (K * M^2 / 1e6)
+ * microseconds of wall time and writes nothing.  `arena` is only used as an
+ * address range (may be any non-NULL value).  For CPU tests of admission,
+ * budget, FIFO order and shutdown; needs no GPU.
+ */
+dop_status dop_serve_create_mock(void *arena, size_t arena_bytes,
+                                 int max_slots, double service_us_per_mpix,
+                                 dop_server **out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DOP_H_ */

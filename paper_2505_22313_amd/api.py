@@ -1,0 +1,304 @@
+"""Python binding of libdop: argument marshalling only.
+
+Every step of the propagation runs in the HIP library; this module checks
+tensor shapes/dtypes/devices, passes raw device pointers and the current
+HIP stream through the C ABI, and raises on any error status.  PyTorch is
+used only for device memory and streams.
+"""
+
+import ctypes
+import threading
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import DopError, DopProblem, DopServeStats, check, lib
+
+OUT_MODES = {"crop": L.DOP_OUT_CROP, "full": L.DOP_OUT_FULL}
+
+
+class Problem:
+    """Problem description (paper Sec. 3.1): DOE grid n x n, padded grid
+    m x m, pitch dx, distance z, wavelengths, refractive indices n(lambda_k)
+    and PSF weights.  Lengths share one unit."""
+
+    def __init__(self, n, m, dx, z, lambdas, n_index, weights=None, out_mode="crop"):
+        self.n, self.m = int(n), int(m)
+        self.dx, self.z = float(dx), float(z)
+        self.lambdas = np.ascontiguousarray(np.atleast_1d(lambdas), dtype=np.float64)
+        self.n_index = np.ascontiguousarray(np.atleast_1d(n_index), dtype=np.float64)
+        if self.lambdas.shape != self.n_index.shape:
+            raise ValueError("lambdas and n_index must have the same length")
+        self.weights = None if weights is None else np.ascontiguousarray(
+            np.atleast_1d(weights), dtype=np.float32)
+        if self.weights is not None and self.weights.shape != self.lambdas.shape:
+            raise ValueError("weights must have one entry per wavelength")
+        if out_mode not in OUT_MODES:
+            raise ValueError("out_mode must be 'crop' or 'full'")
+        self.out_mode = out_mode
+        self._c = DopProblem()
+        c = self._c
+        c.n, c.m, c.dx, c.z = self.n, self.m, self.dx, self.z
+        c.n_lambda = len(self.lambdas)
+        c.lambda_ = self.lambdas.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        c.n_index = self.n_index.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        c.weight = (self.weights.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+                    if self.weights is not None else None)
+        c.out_mode = OUT_MODES[out_mode]
+        c.flags = 0
+
+    @classmethod
+    def from_dict(cls, d, out_mode="crop"):
+        return cls(d["n"], d["m"], d["dx"], d["z"], d["lams"], d["n_index"],
+                   d.get("weights"), out_mode=out_mode)
+
+    @property
+    def k(self):
+        return len(self.lambdas)
+
+    @property
+    def out_shape(self):
+        return (self.n, self.n) if self.out_mode == "crop" else (self.m, self.m)
+
+    def ptr(self):
+        return ctypes.byref(self._c)
+
+
+def workspace_size(prob, op=L.DOP_OP_PSF):
+    out = ctypes.c_size_t(0)
+    check(lib().dop_workspace_size(None, prob.ptr(), op, ctypes.byref(out)), "dop_workspace_size")
+    return out.value
+
+
+class Context:
+    """A libdop context on one HIP device (owns the twiddle table)."""
+
+    def __init__(self, device=None):
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        check(lib().dop_context_create(self.device, ctypes.byref(h)), "dop_context_create")
+        self.handle = h
+        self._ws = {}
+        self._lock = threading.Lock()
+
+    def workspace(self, nbytes, stream):
+        """Cached device workspace of at least nbytes for this stream."""
+        key = int(stream)
+        with self._lock:
+            buf = self._ws.get(key)
+            if buf is None or buf.numel() < nbytes:
+                buf = None
+                self._ws.pop(key, None)
+                buf = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{self.device}")
+                self._ws[key] = buf
+        return buf
+
+    def release_workspaces(self):
+        with self._lock:
+            self._ws.clear()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._ws.clear()
+            lib().dop_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_contexts = {}
+
+
+def default_context(device=None):
+    if device is None:
+        device = torch.cuda.current_device()
+    ctx = _contexts.get(device)
+    if ctx is None:
+        ctx = Context(device)
+        _contexts[device] = ctx
+    return ctx
+
+
+def _stream_handle(device):
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _need(t, name, dtype, shape, device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device.type != "cuda" or t.device.index != device:
+        raise ValueError(f"{name} must live on cuda:{device}, got {t.device}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def propagate(u_in, prob, k=0, ctx=None, out=None):
+    """Eq. (3): propagate an n x n complex64 field by prob.z at wavelength
+    prob.lambdas[k].  Returns n x n (crop) or m x m (full) complex64."""
+    ctx = ctx or default_context(u_in.device.index)
+    dev = ctx.device
+    _need(u_in, "u_in", torch.complex64, (prob.n, prob.n), dev)
+    if out is None:
+        out = torch.empty(prob.out_shape, dtype=torch.complex64, device=u_in.device)
+    _need(out, "out", torch.complex64, prob.out_shape, dev)
+    stream = _stream_handle(dev)
+    nbytes = workspace_size(prob, L.DOP_OP_PROPAGATE)
+    ws = ctx.workspace(nbytes, stream)
+    check(lib().dop_propagate(ctx.handle, prob.ptr(), int(k), _ptr(u_in), _ptr(out), _ptr(ws),
+                              ws.numel(), ctypes.c_void_p(stream)), "dop_propagate")
+    return out
+
+
+def psf(h, prob, amp=None, save_fields=False, ctx=None, out=None):
+    """Eq. (1)-(4): wavelength-summed PSF of height map h (n x n float32).
+    With save_fields=True also returns the K x n x n complex64 fields."""
+    ctx = ctx or default_context(h.device.index)
+    dev = ctx.device
+    _need(h, "h", torch.float32, (prob.n, prob.n), dev)
+    if amp is not None:
+        _need(amp, "amp", torch.float32, (prob.n, prob.n), dev)
+    if out is None:
+        out = torch.empty(prob.out_shape, dtype=torch.float32, device=h.device)
+    _need(out, "out", torch.float32, prob.out_shape, dev)
+    saved = None
+    if save_fields:
+        saved = torch.empty((prob.k, prob.n, prob.n), dtype=torch.complex64, device=h.device)
+    stream = _stream_handle(dev)
+    nbytes = workspace_size(prob, L.DOP_OP_PSF)
+    ws = ctx.workspace(nbytes, stream)
+    check(lib().dop_psf(ctx.handle, prob.ptr(), _ptr(h), _ptr(amp), _ptr(out), _ptr(saved),
+                        _ptr(ws), ws.numel(), ctypes.c_void_p(stream)), "dop_psf")
+    return (out, saved) if save_fields else out
+
+
+def psf_backward(h, prob, saved_u, grad_psf, amp=None, ctx=None, out=None):
+    """dL/dh given dL/dPSF (crop) and the fields saved by psf()."""
+    ctx = ctx or default_context(h.device.index)
+    dev = ctx.device
+    _need(h, "h", torch.float32, (prob.n, prob.n), dev)
+    _need(saved_u, "saved_u", torch.complex64, (prob.k, prob.n, prob.n), dev)
+    _need(grad_psf, "grad_psf", torch.float32, (prob.n, prob.n), dev)
+    if amp is not None:
+        _need(amp, "amp", torch.float32, (prob.n, prob.n), dev)
+    if out is None:
+        out = torch.empty((prob.n, prob.n), dtype=torch.float32, device=h.device)
+    _need(out, "out", torch.float32, (prob.n, prob.n), dev)
+    stream = _stream_handle(dev)
+    nbytes = workspace_size(prob, L.DOP_OP_PSF_BACKWARD)
+    ws = ctx.workspace(nbytes, stream)
+    check(lib().dop_psf_backward(ctx.handle, prob.ptr(), _ptr(h), _ptr(amp), _ptr(saved_u),
+                                 _ptr(grad_psf), _ptr(out), _ptr(ws), ws.numel(),
+                                 ctypes.c_void_p(stream)), "dop_psf_backward")
+    return out
+
+
+class DopPSF(torch.autograd.Function):
+    """PSF(h) with the hand-written adjoint as its backward (crop output)."""
+
+    @staticmethod
+    def forward(fctx, h, prob, amp=None):
+        out, saved = psf(h.detach().contiguous(), prob, amp=amp, save_fields=True)
+        fctx.prob = prob
+        fctx.amp = amp
+        fctx.save_for_backward(h, saved)
+        return out
+
+    @staticmethod
+    def backward(fctx, grad_out):
+        h, saved = fctx.saved_tensors
+        g = psf_backward(h.detach().contiguous(), fctx.prob, saved,
+                         grad_out.contiguous().to(torch.float32), amp=fctx.amp)
+        return g, None, None
+
+
+def psf_autograd(h, prob, amp=None):
+    return DopPSF.apply(h, prob, amp)
+
+
+class Server:
+    """Continuous-batching PSF server over a device arena (see dop.h)."""
+
+    def __init__(self, arena_bytes, max_slots=4, ctx=None, mock_us_per_mpix=None):
+        self.mock = mock_us_per_mpix is not None
+        h = ctypes.c_void_p()
+        if self.mock:
+            self._arena = None
+            check(lib().dop_serve_create_mock(ctypes.c_void_p(256), int(arena_bytes),
+                                              int(max_slots), float(mock_us_per_mpix),
+                                              ctypes.byref(h)), "dop_serve_create_mock")
+        else:
+            self.ctx = ctx or default_context()
+            self._arena = torch.empty(int(arena_bytes), dtype=torch.uint8,
+                                      device=f"cuda:{self.ctx.device}")
+            torch.cuda.synchronize(self.ctx.device)
+            check(lib().dop_serve_create(self.ctx.handle, _ptr(self._arena), int(arena_bytes),
+                                         int(max_slots), ctypes.byref(h)), "dop_serve_create")
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, prob, h, out, amp=None):
+        """Queue a PSF request; h/amp/out are device tensors (or, for a mock
+        server, any integers standing in for addresses).  Returns the
+        ticket."""
+        t = ctypes.c_uint64(0)
+        if self.mock:
+            hp, ap, op = ctypes.c_void_p(int(h)), None, ctypes.c_void_p(int(out))
+        else:
+            dev = self.ctx.device
+            _need(h, "h", torch.float32, (prob.n, prob.n), dev)
+            _need(out, "out", torch.float32, prob.out_shape, dev)
+            if amp is not None:
+                _need(amp, "amp", torch.float32, (prob.n, prob.n), dev)
+            hp, ap, op = _ptr(h), _ptr(amp), _ptr(out)
+        check(lib().dop_serve_submit(self.handle, prob.ptr(), hp, ap, op, ctypes.byref(t)),
+              "dop_serve_submit")
+        self._keep[t.value] = (prob, h, out, amp)
+        return t.value
+
+    def poll(self, ticket):
+        return lib().dop_serve_poll(self.handle, ticket)
+
+    def wait(self, ticket, timeout_s=-1.0):
+        st = lib().dop_serve_wait(self.handle, ticket, float(timeout_s))
+        if st != L.DOP_OK:
+            raise DopError(st, "dop_serve_wait", L.last_error())
+        self._keep.pop(ticket, None)
+        return st
+
+    def latency_ms(self, ticket):
+        v = ctypes.c_double(0)
+        check(lib().dop_serve_latency(self.handle, ticket, ctypes.byref(v)), "dop_serve_latency")
+        return v.value
+
+    def stats(self):
+        s = DopServeStats()
+        check(lib().dop_serve_stats_get(self.handle, ctypes.byref(s)), "dop_serve_stats_get")
+        return {f: getattr(s, f) for f, _ in DopServeStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().dop_serve_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

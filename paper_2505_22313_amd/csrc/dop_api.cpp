@@ -1,0 +1,320 @@
+// libdop C ABI: argument validation, context (twiddle table), workspace query
+// and the per-wavelength orchestration of the propagation passes.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dop.h"
+#include "dop_internal.h"
+#include "dop_host.h"
+
+struct dop_context {
+  int device = 0;
+  float2 *tw = nullptr;  // kTwN complex64 twiddles exp(-2 pi i j / kTwN)
+};
+
+namespace dop {
+
+static thread_local std::string g_last_error;
+
+dop_status fail(dop_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+static int ilog2i(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+dop_status validate_problem(const dop_problem *prob) {
+  if (!prob) return fail(DOP_ERR_INVALID_ARG, "problem is NULL");
+  if (prob->n < 1) return fail(DOP_ERR_INVALID_ARG, "n must be >= 1 (got %d)", prob->n);
+  if (prob->m < 1) return fail(DOP_ERR_INVALID_ARG, "m must be >= 1 (got %d)", prob->m);
+  if (!is_pow2(prob->m) || prob->m < DOP_MIN_M || prob->m > DOP_MAX_M)
+    return fail(DOP_ERR_UNSUPPORTED, "m must be a power of two in [%d, %d] (got %d)", DOP_MIN_M,
+                DOP_MAX_M, prob->m);
+  if (prob->n > prob->m) return fail(DOP_ERR_INVALID_ARG, "n (%d) exceeds m (%d)", prob->n, prob->m);
+  if (!(prob->dx > 0.0) || !std::isfinite(prob->dx))
+    return fail(DOP_ERR_INVALID_ARG, "dx must be finite and > 0");
+  if (!std::isfinite(prob->z)) return fail(DOP_ERR_INVALID_ARG, "z must be finite");
+  if (prob->n_lambda < 1 || prob->n_lambda > DOP_MAX_LAMBDA)
+    return fail(DOP_ERR_INVALID_ARG, "n_lambda must be in [1, %d] (got %d)", DOP_MAX_LAMBDA,
+                prob->n_lambda);
+  if (!prob->lambda) return fail(DOP_ERR_INVALID_ARG, "lambda array is NULL");
+  if (!prob->n_index) return fail(DOP_ERR_INVALID_ARG, "n_index array is NULL");
+  for (int k = 0; k < prob->n_lambda; ++k) {
+    if (!(prob->lambda[k] > 0.0) || !std::isfinite(prob->lambda[k]))
+      return fail(DOP_ERR_INVALID_ARG, "lambda[%d] must be finite and > 0", k);
+    if (!std::isfinite(prob->n_index[k]))
+      return fail(DOP_ERR_INVALID_ARG, "n_index[%d] must be finite", k);
+    if (prob->weight && !std::isfinite(prob->weight[k]))
+      return fail(DOP_ERR_INVALID_ARG, "weight[%d] must be finite", k);
+  }
+  if (prob->out_mode != DOP_OUT_CROP && prob->out_mode != DOP_OUT_FULL)
+    return fail(DOP_ERR_INVALID_ARG, "out_mode must be DOP_OUT_CROP or DOP_OUT_FULL");
+  if (prob->flags != 0) return fail(DOP_ERR_UNSUPPORTED, "flags must be 0");
+  // The phase and transfer arguments are reduced in FP64; beyond ~2^40 turns
+  // their fractional part would carry no bits.
+  for (int k = 0; k < prob->n_lambda; ++k) {
+    if (std::fabs(prob->z / prob->lambda[k]) > 1e12)
+      return fail(DOP_ERR_UNSUPPORTED, "|z / lambda[%d]| exceeds 1e12 turns", k);
+  }
+  return DOP_OK;
+}
+
+size_t workspace_bytes(const dop_problem *prob) {
+  return (size_t)prob->m * (size_t)prob->m * sizeof(float2);
+}
+
+// Fill the per-wavelength kernel parameters shared by every operation.
+void fill_common(KParams &kp, const dop_context *ctx, const dop_problem *prob, int k, void *ws) {
+  std::memset(&kp, 0, sizeof(kp));
+  kp.ws = static_cast<float2 *>(ws);
+  kp.tw = ctx->tw;
+  kp.n = prob->n;
+  kp.m = prob->m;
+  kp.logm = ilog2i(prob->m);
+  kp.nrows_in = prob->n;
+  kp.p0 = (prob->m - prob->n) / 2;
+  const double lam = prob->lambda[k];
+  kp.lam = lam;
+  kp.zl = prob->z / lam;
+  kp.inv_mdx = 1.0 / ((double)prob->m * prob->dx);
+  kp.phase_turns = (prob->n_index[k] - 1.0) / lam;
+  const float w = prob->weight ? prob->weight[k] : 1.0f;
+  kp.wk = w;
+  kp.two_wk = 2.0f * w;
+  kp.ck = (float)(2.0 * M_PI * (prob->n_index[k] - 1.0) / lam);
+  kp.inv_m2 = (float)(1.0 / ((double)prob->m * (double)prob->m));
+}
+
+dop_status launch(const KParams &kp, hipStream_t stream) {
+  const hipError_t e = launch_wavelength(kp, stream);
+  if (e != hipSuccess) return fail(DOP_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return DOP_OK;
+}
+
+dop_status check_ctx_device(const dop_context *ctx) {
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(DOP_ERR_DEVICE, "hipGetDevice failed");
+  if (cur != ctx->device)
+    return fail(DOP_ERR_INVALID_ARG, "current HIP device %d differs from the context's device %d",
+                cur, ctx->device);
+  return DOP_OK;
+}
+
+dop_status enqueue_psf(const dop_context *ctx, const dop_problem *prob, const float *h,
+                       const float *amp, float *psf, void *saved_u, void *ws, hipStream_t stream) {
+  const size_t nn = (size_t)prob->n * prob->n;
+  for (int k = 0; k < prob->n_lambda; ++k) {
+    KParams kp;
+    fill_common(kp, ctx, prob, k, ws);
+    kp.in_mode = IN_PHASE;
+    kp.out_mode = OUT_PSF;
+    kp.full = prob->out_mode == DOP_OUT_FULL;
+    kp.nrows_out = kp.full ? prob->m : prob->n;
+    kp.first = (k == 0);
+    kp.h = h;
+    kp.amp = amp;
+    kp.psf = psf;
+    kp.saved_out = saved_u ? static_cast<float2 *>(saved_u) + (size_t)k * nn : nullptr;
+    const dop_status s = launch(kp, stream);
+    if (s != DOP_OK) return s;
+  }
+  return DOP_OK;
+}
+
+}  // namespace dop
+
+using namespace dop;
+
+extern "C" {
+
+const char *dop_status_string(dop_status s) {
+  switch (s) {
+    case DOP_OK: return "DOP_OK";
+    case DOP_NOT_READY: return "DOP_NOT_READY";
+    case DOP_ERR_INVALID_ARG: return "DOP_ERR_INVALID_ARG";
+    case DOP_ERR_UNSUPPORTED: return "DOP_ERR_UNSUPPORTED";
+    case DOP_ERR_WORKSPACE: return "DOP_ERR_WORKSPACE";
+    case DOP_ERR_DEVICE: return "DOP_ERR_DEVICE";
+    case DOP_ERR_BUDGET: return "DOP_ERR_BUDGET";
+    case DOP_ERR_NOT_FOUND: return "DOP_ERR_NOT_FOUND";
+    case DOP_ERR_SHUTDOWN: return "DOP_ERR_SHUTDOWN";
+    case DOP_ERR_TIMEOUT: return "DOP_ERR_TIMEOUT";
+  }
+  return "DOP_UNKNOWN_STATUS";
+}
+
+const char *dop_last_error(void) { return g_last_error.c_str(); }
+
+dop_status dop_context_create(int device, dop_context **out) {
+  clear_error();
+  if (!out) return fail(DOP_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
+    return fail(DOP_ERR_DEVICE, "no HIP device available");
+  if (device < 0 || device >= count)
+    return fail(DOP_ERR_INVALID_ARG, "device %d out of range [0, %d)", device, count);
+  int prev = 0;
+  hipGetDevice(&prev);
+  if (hipSetDevice(device) != hipSuccess) return fail(DOP_ERR_DEVICE, "hipSetDevice(%d) failed", device);
+  // FP64-generated twiddles, rounded once to complex64.
+  std::vector<float2> host(kTwN);
+  for (int j = 0; j < kTwN; ++j) {
+    const double a = -2.0 * M_PI * (double)j / (double)kTwN;
+    host[j] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  dop_context *ctx = new dop_context();
+  ctx->device = device;
+  hipError_t e = hipMalloc(reinterpret_cast<void **>(&ctx->tw), sizeof(float2) * kTwN);
+  if (e == hipSuccess)
+    e = hipMemcpy(ctx->tw, host.data(), sizeof(float2) * kTwN, hipMemcpyHostToDevice);
+  hipSetDevice(prev);
+  if (e != hipSuccess) {
+    if (ctx->tw) hipFree(ctx->tw);
+    delete ctx;
+    return fail(DOP_ERR_DEVICE, "twiddle upload failed: %s", hipGetErrorString(e));
+  }
+  *out = ctx;
+  return DOP_OK;
+}
+
+dop_status dop_context_destroy(dop_context *ctx) {
+  clear_error();
+  if (!ctx) return fail(DOP_ERR_INVALID_ARG, "context is NULL");
+  if (ctx->tw) {
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(ctx->device);
+    hipFree(ctx->tw);
+    hipSetDevice(prev);
+  }
+  delete ctx;
+  return DOP_OK;
+}
+
+dop_status dop_workspace_size(const dop_context *ctx, const dop_problem *prob, int op,
+                              size_t *bytes) {
+  clear_error();
+  (void)ctx;
+  if (!bytes) return fail(DOP_ERR_INVALID_ARG, "bytes is NULL");
+  if (op != DOP_OP_PROPAGATE && op != DOP_OP_PSF && op != DOP_OP_PSF_BACKWARD)
+    return fail(DOP_ERR_INVALID_ARG, "unknown op %d", op);
+  const dop_status s = validate_problem(prob);
+  if (s != DOP_OK) return s;
+  *bytes = workspace_bytes(prob);
+  return DOP_OK;
+}
+
+static dop_status check_ws(const dop_problem *prob, void *ws, size_t ws_bytes) {
+  if (!ws) return fail(DOP_ERR_WORKSPACE, "workspace is NULL");
+  if (ws_bytes < workspace_bytes(prob))
+    return fail(DOP_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes,
+                workspace_bytes(prob));
+  if (reinterpret_cast<uintptr_t>(ws) % 16 != 0)
+    return fail(DOP_ERR_WORKSPACE, "workspace must be 16-byte aligned");
+  return DOP_OK;
+}
+
+static bool aligned(const void *p, size_t a) { return reinterpret_cast<uintptr_t>(p) % a == 0; }
+
+dop_status dop_propagate(dop_context *ctx, const dop_problem *prob, int k, const void *u_in,
+                         void *u_out, void *ws, size_t ws_bytes, void *stream) {
+  clear_error();
+  if (!ctx) return fail(DOP_ERR_INVALID_ARG, "context is NULL");
+  dop_status s = validate_problem(prob);
+  if (s != DOP_OK) return s;
+  if (k < 0 || k >= prob->n_lambda)
+    return fail(DOP_ERR_INVALID_ARG, "k=%d out of range [0, %d)", k, prob->n_lambda);
+  if (!u_in || !u_out) return fail(DOP_ERR_INVALID_ARG, "u_in / u_out must not be NULL");
+  if (!aligned(u_in, 8) || !aligned(u_out, 8))
+    return fail(DOP_ERR_INVALID_ARG, "complex arrays must be 8-byte aligned");
+  if ((s = check_ws(prob, ws, ws_bytes)) != DOP_OK) return s;
+  if ((s = check_ctx_device(ctx)) != DOP_OK) return s;
+  KParams kp;
+  fill_common(kp, ctx, prob, k, ws);
+  kp.in_mode = IN_FIELD;
+  kp.out_mode = OUT_FIELD;
+  kp.full = prob->out_mode == DOP_OUT_FULL;
+  kp.nrows_out = kp.full ? prob->m : prob->n;
+  kp.first = 1;
+  kp.u_in = static_cast<const float2 *>(u_in);
+  kp.u_out = static_cast<float2 *>(u_out);
+  return launch(kp, static_cast<hipStream_t>(stream));
+}
+
+dop_status dop_psf(dop_context *ctx, const dop_problem *prob, const float *h, const float *amp,
+                   float *psf, void *saved_u, void *ws, size_t ws_bytes, void *stream) {
+  clear_error();
+  if (!ctx) return fail(DOP_ERR_INVALID_ARG, "context is NULL");
+  dop_status s = validate_problem(prob);
+  if (s != DOP_OK) return s;
+  if (!h || !psf) return fail(DOP_ERR_INVALID_ARG, "h / psf must not be NULL");
+  if (!aligned(h, 4) || !aligned(psf, 4) || (amp && !aligned(amp, 4)))
+    return fail(DOP_ERR_INVALID_ARG, "float arrays must be 4-byte aligned");
+  if (saved_u && prob->out_mode != DOP_OUT_CROP)
+    return fail(DOP_ERR_UNSUPPORTED, "saved_u requires DOP_OUT_CROP");
+  if (saved_u && !aligned(saved_u, 8))
+    return fail(DOP_ERR_INVALID_ARG, "saved_u must be 8-byte aligned");
+  if ((s = check_ws(prob, ws, ws_bytes)) != DOP_OK) return s;
+  if ((s = check_ctx_device(ctx)) != DOP_OK) return s;
+  return enqueue_psf(ctx, prob, h, amp, psf, saved_u, ws, static_cast<hipStream_t>(stream));
+}
+
+dop_status dop_psf_backward(dop_context *ctx, const dop_problem *prob, const float *h,
+                            const float *amp, const void *saved_u, const float *grad_psf,
+                            float *grad_h, void *ws, size_t ws_bytes, void *stream) {
+  clear_error();
+  if (!ctx) return fail(DOP_ERR_INVALID_ARG, "context is NULL");
+  dop_status s = validate_problem(prob);
+  if (s != DOP_OK) return s;
+  if (prob->out_mode != DOP_OUT_CROP)
+    return fail(DOP_ERR_UNSUPPORTED, "dop_psf_backward supports DOP_OUT_CROP only");
+  if (!h || !saved_u || !grad_psf || !grad_h)
+    return fail(DOP_ERR_INVALID_ARG, "h / saved_u / grad_psf / grad_h must not be NULL");
+  if (!aligned(h, 4) || !aligned(grad_psf, 4) || !aligned(grad_h, 4) || !aligned(saved_u, 8) ||
+      (amp && !aligned(amp, 4)))
+    return fail(DOP_ERR_INVALID_ARG, "misaligned array");
+  if ((s = check_ws(prob, ws, ws_bytes)) != DOP_OK) return s;
+  if ((s = check_ctx_device(ctx)) != DOP_OK) return s;
+  const size_t nn = (size_t)prob->n * prob->n;
+  for (int k = 0; k < prob->n_lambda; ++k) {
+    KParams kp;
+    fill_common(kp, ctx, prob, k, ws);
+    kp.in_mode = IN_GRAD;
+    kp.out_mode = OUT_GRADH;
+    kp.full = 0;
+    kp.nrows_out = prob->n;
+    kp.first = (k == 0);
+    kp.adjoint = 1;
+    kp.h = h;
+    kp.amp = amp;
+    kp.gpsf = grad_psf;
+    kp.saved_in = static_cast<const float2 *>(saved_u) + (size_t)k * nn;
+    kp.grad_h = grad_h;
+    s = launch(kp, static_cast<hipStream_t>(stream));
+    if (s != DOP_OK) return s;
+  }
+  return DOP_OK;
+}
+
+}  // extern "C"
+
+int dop::context_device(const dop_context *ctx) { return ctx->device; }

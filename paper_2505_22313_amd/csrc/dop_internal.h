@@ -1,0 +1,73 @@
+// Internal declarations shared by the libdop host code and its HIP kernels.
+#ifndef DOP_INTERNAL_H_
+#define DOP_INTERNAL_H_
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace dop {
+
+// Size of the shared twiddle table: W[j] = exp(-2 pi i j / kTwN).
+constexpr int kTwLog = 16;
+constexpr int kTwN = 1 << kTwLog;
+
+// Pass-A input modes.
+enum InMode : int {
+  IN_PHASE = 0,  // E = amp * exp(i 2 pi (n-1)/lambda h)        (Eq. 1-2)
+  IN_FIELD = 1,  // caller's complex field
+  IN_GRAD = 2    // g_U = 2 w_k G * U_k (adjoint seed)
+};
+
+// Last-pass output modes.
+enum OutMode : int {
+  OUT_PSF = 0,    // psf (+)= w_k |U|^2                          (Eq. 4)
+  OUT_FIELD = 1,  // complex U
+  OUT_GRADH = 2   // grad_h (+)= c_k Im(g_E conj(E_k))
+};
+
+// Everything one wavelength's five passes need.  Passed by value.
+struct KParams {
+  float2 *ws;            // M x M c64 workspace
+  const float2 *tw;      // twiddle table, kTwN entries
+  int n, m, logm;
+  int nrows_in;          // rows of the padded input that may be nonzero
+  int nrows_out;         // rows of the output plane that are needed
+  int p0;                // (M - N) / 2
+  int in_mode, out_mode;
+  int full;              // 1: output the whole M x M plane (centred)
+  int first;             // 1: overwrite the accumulator, 0: add to it
+  int adjoint;           // 1: multiply by conj(H)
+  const float *h;        // N x N heights (IN_PHASE, OUT_GRADH)
+  const float *amp;      // N x N amplitude or NULL
+  const float2 *u_in;    // N x N field (IN_FIELD)
+  const float2 *saved_in;// N x N field U_k (IN_GRAD)
+  const float *gpsf;     // N x N dL/dPSF (IN_GRAD)
+  float *psf;            // OUT_PSF destination
+  float2 *u_out;         // OUT_FIELD destination
+  float2 *saved_out;     // optional N x N copy of U_k (OUT_PSF, crop)
+  float *grad_h;         // OUT_GRADH destination
+  double phase_turns;    // (n_k - 1) / lambda_k  (turns of phase per unit h)
+  double zl;             // z / lambda_k          (turns at normal incidence)
+  double lam;            // lambda_k
+  double inv_mdx;        // 1 / (M dx)
+  float wk;              // PSF weight w_k
+  float two_wk;          // 2 w_k
+  float ck;              // 2 pi (n_k - 1) / lambda_k
+  float inv_m2;          // 1 / M^2 (inverse-FFT normalisation)
+};
+
+// Enqueue the five passes of one wavelength on `stream`.
+hipError_t launch_wavelength(const KParams &p, hipStream_t stream);
+
+// Tile geometry of the pass plan for a given log2(M) (host-side copy of the
+// compile-time plan, used for reporting and tests).
+struct PlanInfo {
+  int ax, bx, ay, by, ra, rc;
+  int threads_a, threads_b, threads_c;
+};
+bool plan_info(int logm, PlanInfo *out);
+
+}  // namespace dop
+
+#endif  // DOP_INTERNAL_H_

@@ -148,6 +148,27 @@ dop_status dop_psf_backward(dop_context *ctx, const dop_problem *prob,
                             void *stream);
 
 /* ------------------------------------------------------------------------
+ * Per-pass timing.  While enabled, every wavelength's five passes are
+ * bracketed by HIP events on the stream they run on; dop_profile_read waits
+ * for the recorded events and returns, per pass, the launch count and the
+ * summed event-to-event time.  Enabling clears the accumulators.  Timing
+ * adds one event record between consecutive passes and is off by default.
+ * Pass names: "pass_a_fwd", "pass_b_fwd", "pass_c", "pass_b_inv",
+ * "pass_a_inv" (the kernels dop::k_pass_*<log2 M>).
+ * ---------------------------------------------------------------------- */
+
+#define DOP_NUM_PASSES 5
+
+typedef struct {
+  char name[32];
+  uint64_t launches;
+  double total_ms;
+} dop_pass_profile;
+
+dop_status dop_profile_enable(dop_context *ctx, int enable);
+dop_status dop_profile_read(dop_context *ctx, dop_pass_profile *out, int max, int *count);
+
+/* ------------------------------------------------------------------------
  * Serving: continuous batching of PSF requests (dop_psf, CROP or FULL) of
  * mixed sizes and wavelength counts.  The server sub-allocates workspaces
  * from a caller-provided device arena (it never calls hipMalloc per request),

@@ -63,6 +63,14 @@ class DopServeStats(ctypes.Structure):
     ]
 
 
+class DopPassProfile(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 32),
+        ("launches", ctypes.c_uint64),
+        ("total_ms", ctypes.c_double),
+    ]
+
+
 class DopError(RuntimeError):
     def __init__(self, status, where, detail):
         self.status = status
@@ -92,6 +100,9 @@ _SIGNATURES = {
     "dop_serve_latency": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]),
     "dop_serve_stats_get": (ctypes.c_int, [_VP, ctypes.POINTER(DopServeStats)]),
     "dop_serve_destroy": (ctypes.c_int, [_VP]),
+    "dop_profile_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
+    "dop_profile_read": (ctypes.c_int, [_VP, ctypes.POINTER(DopPassProfile), ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int)]),
 }
 
 

@@ -96,6 +96,17 @@ class Context:
                 self._ws[key] = buf
         return buf
 
+    def profile_enable(self, enable=True):
+        """Start (clearing the totals) or stop per-pass HIP-event timing."""
+        check(lib().dop_profile_enable(self.handle, 1 if enable else 0), "dop_profile_enable")
+
+    def profile_read(self):
+        """{pass name: (launches, total ms)} of the timed launches so far."""
+        arr = (L.DopPassProfile * 8)()
+        cnt = ctypes.c_int(0)
+        check(lib().dop_profile_read(self.handle, arr, 8, ctypes.byref(cnt)), "dop_profile_read")
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(cnt.value)}
+
     def release_workspaces(self):
         with self._lock:
             self._ws.clear()

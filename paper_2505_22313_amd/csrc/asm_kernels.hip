@@ -604,36 +604,46 @@ __global__ __launch_bounds__(Plan<LOGM>::TA) void k_pass_a_inv(KParams p) {
 // ---------------------------------------------------------------------------
 // Host-side launch of the five passes.
 // ---------------------------------------------------------------------------
+static inline void mark(hipEvent_t *ev, int i, hipStream_t s) {
+  if (ev) (void)hipEventRecord(ev[i], s);
+}
+
 template <int LOGM>
-static hipError_t launch_impl(const KParams &p, hipStream_t s) {
+static hipError_t launch_impl(const KParams &p, hipStream_t s, hipEvent_t *ev) {
   using P = Plan<LOGM>;
   const unsigned ga = (unsigned)p.nrows_in * (P::BX / P::RA);
   const unsigned gb = (unsigned)(P::AX * P::BY);
   const unsigned gc = (unsigned)(P::AY * (P::M / P::RC));
   const unsigned gai = (unsigned)p.nrows_out * (P::BX / P::RA);
+  mark(ev, 0, s);
   hipLaunchKernelGGL(k_pass_a_fwd<LOGM>, dim3(ga), dim3(P::TA), 0, s, p);
+  mark(ev, 1, s);
   hipLaunchKernelGGL(k_pass_b_fwd<LOGM>, dim3(gb), dim3(P::TB), 0, s, p);
+  mark(ev, 2, s);
   hipLaunchKernelGGL(k_pass_c<LOGM>, dim3(gc), dim3(P::TC), 0, s, p);
+  mark(ev, 3, s);
   hipLaunchKernelGGL(k_pass_b_inv<LOGM>, dim3(gb), dim3(P::TB), 0, s, p);
+  mark(ev, 4, s);
   hipLaunchKernelGGL(k_pass_a_inv<LOGM>, dim3(gai), dim3(P::TA), 0, s, p);
+  mark(ev, 5, s);
   return hipGetLastError();
 }
 
-hipError_t launch_wavelength(const KParams &p, hipStream_t s) {
+hipError_t launch_wavelength(const KParams &p, hipStream_t s, hipEvent_t *ev) {
   switch (p.logm) {
-    case 4: return launch_impl<4>(p, s);
-    case 5: return launch_impl<5>(p, s);
-    case 6: return launch_impl<6>(p, s);
-    case 7: return launch_impl<7>(p, s);
-    case 8: return launch_impl<8>(p, s);
-    case 9: return launch_impl<9>(p, s);
-    case 10: return launch_impl<10>(p, s);
-    case 11: return launch_impl<11>(p, s);
-    case 12: return launch_impl<12>(p, s);
-    case 13: return launch_impl<13>(p, s);
-    case 14: return launch_impl<14>(p, s);
-    case 15: return launch_impl<15>(p, s);
-    case 16: return launch_impl<16>(p, s);
+    case 4: return launch_impl<4>(p, s, ev);
+    case 5: return launch_impl<5>(p, s, ev);
+    case 6: return launch_impl<6>(p, s, ev);
+    case 7: return launch_impl<7>(p, s, ev);
+    case 8: return launch_impl<8>(p, s, ev);
+    case 9: return launch_impl<9>(p, s, ev);
+    case 10: return launch_impl<10>(p, s, ev);
+    case 11: return launch_impl<11>(p, s, ev);
+    case 12: return launch_impl<12>(p, s, ev);
+    case 13: return launch_impl<13>(p, s, ev);
+    case 14: return launch_impl<14>(p, s, ev);
+    case 15: return launch_impl<15>(p, s, ev);
+    case 16: return launch_impl<16>(p, s, ev);
     default: return hipErrorInvalidValue;
   }
 }

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -16,6 +17,13 @@
 struct dop_context {
   int device = 0;
   float2 *tw = nullptr;  // kTwN complex64 twiddles exp(-2 pi i j / kTwN)
+  // per-pass timing (off unless enabled)
+  std::mutex prof_mu;
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_pool;            // idle events
+  std::vector<std::vector<hipEvent_t>> pending;  // 6 events per wavelength launch
+  double prof_ms[dop::kNumPasses] = {0, 0, 0, 0, 0};
+  uint64_t prof_n[dop::kNumPasses] = {0, 0, 0, 0, 0};
 };
 
 namespace dop {
@@ -103,8 +111,29 @@ void fill_common(KParams &kp, const dop_context *ctx, const dop_problem *prob, i
   kp.inv_m2 = (float)(1.0 / ((double)prob->m * (double)prob->m));
 }
 
-dop_status launch(const KParams &kp, hipStream_t stream) {
-  const hipError_t e = launch_wavelength(kp, stream);
+dop_status launch(const dop_context *cctx, const KParams &kp, hipStream_t stream) {
+  dop_context *ctx = const_cast<dop_context *>(cctx);
+  std::vector<hipEvent_t> ev;
+  {
+    std::lock_guard<std::mutex> lk(ctx->prof_mu);
+    if (ctx->prof_on) {
+      while ((int)ev.size() < kNumPasses + 1) {
+        hipEvent_t e = nullptr;
+        if (!ctx->prof_pool.empty()) {
+          e = ctx->prof_pool.back();
+          ctx->prof_pool.pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+          return fail(DOP_ERR_DEVICE, "hipEventCreate failed");
+        }
+        ev.push_back(e);
+      }
+    }
+  }
+  const hipError_t e = launch_wavelength(kp, stream, ev.empty() ? nullptr : ev.data());
+  if (!ev.empty()) {
+    std::lock_guard<std::mutex> lk(ctx->prof_mu);
+    ctx->pending.push_back(std::move(ev));
+  }
   if (e != hipSuccess) return fail(DOP_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
   return DOP_OK;
 }
@@ -133,7 +162,7 @@ dop_status enqueue_psf(const dop_context *ctx, const dop_problem *prob, const fl
     kp.amp = amp;
     kp.psf = psf;
     kp.saved_out = saved_u ? static_cast<float2 *>(saved_u) + (size_t)k * nn : nullptr;
-    const dop_status s = launch(kp, stream);
+    const dop_status s = launch(ctx, kp, stream);
     if (s != DOP_OK) return s;
   }
   return DOP_OK;
@@ -173,7 +202,7 @@ dop_status dop_context_create(int device, dop_context **out) {
   if (device < 0 || device >= count)
     return fail(DOP_ERR_INVALID_ARG, "device %d out of range [0, %d)", device, count);
   int prev = 0;
-  hipGetDevice(&prev);
+  (void)hipGetDevice(&prev);
   if (hipSetDevice(device) != hipSuccess) return fail(DOP_ERR_DEVICE, "hipSetDevice(%d) failed", device);
   // FP64-generated twiddles, rounded once to complex64.
   std::vector<float2> host(kTwN);
@@ -186,9 +215,9 @@ dop_status dop_context_create(int device, dop_context **out) {
   hipError_t e = hipMalloc(reinterpret_cast<void **>(&ctx->tw), sizeof(float2) * kTwN);
   if (e == hipSuccess)
     e = hipMemcpy(ctx->tw, host.data(), sizeof(float2) * kTwN, hipMemcpyHostToDevice);
-  hipSetDevice(prev);
+  (void)hipSetDevice(prev);
   if (e != hipSuccess) {
-    if (ctx->tw) hipFree(ctx->tw);
+    if (ctx->tw) (void)hipFree(ctx->tw);
     delete ctx;
     return fail(DOP_ERR_DEVICE, "twiddle upload failed: %s", hipGetErrorString(e));
   }
@@ -199,14 +228,72 @@ dop_status dop_context_create(int device, dop_context **out) {
 dop_status dop_context_destroy(dop_context *ctx) {
   clear_error();
   if (!ctx) return fail(DOP_ERR_INVALID_ARG, "context is NULL");
-  if (ctx->tw) {
-    int prev = 0;
-    hipGetDevice(&prev);
-    hipSetDevice(ctx->device);
-    hipFree(ctx->tw);
-    hipSetDevice(prev);
-  }
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(ctx->device);
+  for (auto &v : ctx->pending)
+    for (hipEvent_t e : v) {
+      (void)hipEventSynchronize(e);
+      (void)hipEventDestroy(e);
+    }
+  for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
+  if (ctx->tw) (void)hipFree(ctx->tw);
+  (void)hipSetDevice(prev);
   delete ctx;
+  return DOP_OK;
+}
+
+static const char *kPassNames[kNumPasses] = {"pass_a_fwd", "pass_b_fwd", "pass_c", "pass_b_inv",
+                                             "pass_a_inv"};
+
+// Wait for the pending events and fold their intervals into the totals.
+static dop_status collect(dop_context *ctx) {
+  for (auto &v : ctx->pending) {
+    if (hipEventSynchronize(v.back()) != hipSuccess)
+      return fail(DOP_ERR_DEVICE, "hipEventSynchronize failed");
+    for (int i = 0; i < kNumPasses; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, v[i], v[i + 1]) != hipSuccess)
+        return fail(DOP_ERR_DEVICE, "hipEventElapsedTime failed");
+      ctx->prof_ms[i] += ms;
+      ctx->prof_n[i] += 1;
+    }
+    for (hipEvent_t e : v) ctx->prof_pool.push_back(e);
+  }
+  ctx->pending.clear();
+  return DOP_OK;
+}
+
+dop_status dop_profile_enable(dop_context *ctx, int enable) {
+  clear_error();
+  if (!ctx) return fail(DOP_ERR_INVALID_ARG, "context is NULL");
+  std::lock_guard<std::mutex> lk(ctx->prof_mu);
+  const dop_status s = collect(ctx);
+  if (s != DOP_OK) return s;
+  if (enable) {
+    for (int i = 0; i < kNumPasses; ++i) {
+      ctx->prof_ms[i] = 0;
+      ctx->prof_n[i] = 0;
+    }
+  }
+  ctx->prof_on = enable != 0;
+  return DOP_OK;
+}
+
+dop_status dop_profile_read(dop_context *ctx, dop_pass_profile *out, int max, int *count) {
+  clear_error();
+  if (!ctx || !out || !count) return fail(DOP_ERR_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(ctx->prof_mu);
+  const dop_status s = collect(ctx);
+  if (s != DOP_OK) return s;
+  const int n = max < kNumPasses ? max : kNumPasses;
+  for (int i = 0; i < n; ++i) {
+    std::memset(&out[i], 0, sizeof(out[i]));
+    std::strncpy(out[i].name, kPassNames[i], sizeof(out[i].name) - 1);
+    out[i].launches = ctx->prof_n[i];
+    out[i].total_ms = ctx->prof_ms[i];
+  }
+  *count = n;
   return DOP_OK;
 }
 
@@ -257,7 +344,7 @@ dop_status dop_propagate(dop_context *ctx, const dop_problem *prob, int k, const
   kp.first = 1;
   kp.u_in = static_cast<const float2 *>(u_in);
   kp.u_out = static_cast<float2 *>(u_out);
-  return launch(kp, static_cast<hipStream_t>(stream));
+  return launch(ctx, kp, static_cast<hipStream_t>(stream));
 }
 
 dop_status dop_psf(dop_context *ctx, const dop_problem *prob, const float *h, const float *amp,
@@ -309,7 +396,7 @@ dop_status dop_psf_backward(dop_context *ctx, const dop_problem *prob, const flo
     kp.gpsf = grad_psf;
     kp.saved_in = static_cast<const float2 *>(saved_u) + (size_t)k * nn;
     kp.grad_h = grad_h;
-    s = launch(kp, static_cast<hipStream_t>(stream));
+    s = launch(ctx, kp, static_cast<hipStream_t>(stream));
     if (s != DOP_OK) return s;
   }
   return DOP_OK;

@@ -57,8 +57,12 @@ struct KParams {
   float inv_m2;          // 1 / M^2 (inverse-FFT normalisation)
 };
 
-// Enqueue the five passes of one wavelength on `stream`.
-hipError_t launch_wavelength(const KParams &p, hipStream_t stream);
+constexpr int kNumPasses = 5;
+
+// Enqueue the five passes of one wavelength on `stream`.  If `ev` is not
+// NULL, ev[0..5] are recorded before the first pass, between passes and
+// after the last one.
+hipError_t launch_wavelength(const KParams &p, hipStream_t stream, hipEvent_t *ev);
 
 // Tile geometry of the pass plan for a given log2(M) (host-side copy of the
 // compile-time plan, used for reporting and tests).

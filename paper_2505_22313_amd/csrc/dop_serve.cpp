@@ -108,7 +108,7 @@ class GpuExecutor : public Executor {
  public:
   GpuExecutor(dop_context *ctx, int slots) : ctx_(ctx), streams_(slots), events_(slots) {}
   dop_status init() {
-    hipSetDevice(context_device(ctx_));
+    (void)hipSetDevice(context_device(ctx_));
     for (size_t i = 0; i < streams_.size(); ++i) {
       if (hipStreamCreateWithFlags(&streams_[i], hipStreamNonBlocking) != hipSuccess)
         return fail(DOP_ERR_DEVICE, "hipStreamCreate failed");
@@ -119,13 +119,13 @@ class GpuExecutor : public Executor {
   }
   ~GpuExecutor() override {
     for (auto s : streams_)
-      if (s) hipStreamSynchronize(s);
+      if (s) (void)hipStreamSynchronize(s);
     for (auto e : events_)
-      if (e) hipEventDestroy(e);
+      if (e) (void)hipEventDestroy(e);
     for (auto s : streams_)
-      if (s) hipStreamDestroy(s);
+      if (s) (void)hipStreamDestroy(s);
   }
-  void thread_init() override { hipSetDevice(context_device(ctx_)); }
+  void thread_init() override { (void)hipSetDevice(context_device(ctx_)); }
   dop_status start(int slot, Request &r, void *ws, size_t) override {
     dop_status s = enqueue_psf(ctx_, &r.prob, r.h, r.amp, r.psf, nullptr, ws, streams_[slot]);
     if (s != DOP_OK) return s;

@@ -28,8 +28,23 @@ index (lambda0 / (n(lambda0) - 1) = 1.19 um), the depth the paper's
 lithography is calibrated to (Sec. 3.2, contrast-curve footnote).
 """
 
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import scipy.fft as sfft
+
+
+def _threads():
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _parallel_rows(n, block, fn):
+    """Run fn(r0, r1) over row blocks of [0, n) on a thread pool (NumPy
+    releases the GIL inside its kernels)."""
+    spans = [(r0, min(n, r0 + block)) for r0 in range(0, n, block)]
+    with ThreadPoolExecutor(_threads()) as ex:
+        list(ex.map(lambda s: fn(*s), spans))
 
 LAMBDA0 = 0.55  # um, nominal design wavelength
 
@@ -63,8 +78,8 @@ def fresnel_lens_heights(n, dx, f, lam0=LAMBDA0, levels=0, row_block=2048):
     c = pixel_coords(n, dx)
     out = np.empty((n, n), dtype=np.float32)
     x2 = c * c
-    for r0 in range(0, n, row_block):
-        r1 = min(n, r0 + row_block)
+
+    def rows(r0, r1):
         r2 = x2[r0:r1, None] + x2[None, :]
         turns = -(np.sqrt(r2 + f * f) - f) / lam0
         frac = turns - np.floor(turns)  # wrapped phase / (2 pi), in [0, 1)
@@ -73,6 +88,8 @@ def fresnel_lens_heights(n, dx, f, lam0=LAMBDA0, levels=0, row_block=2048):
             step = hmax / levels
             h = np.floor(h / step) * step
         out[r0:r1] = h.astype(np.float32)
+
+    _parallel_rows(n, min(row_block, 512), rows)
     return out
 
 
@@ -84,8 +101,17 @@ def smooth_noise(n, seed, sigma_px=8.0, std=0.02, truncate=4.0):
     The blur is the circular convolution with the separable truncated kernel,
     applied through its DFT along each axis.
     """
-    rng = np.random.default_rng(seed)
-    noise = rng.standard_normal((n, n), dtype=np.float32)
+    # one PCG64 stream per block of rows, spawned from `seed`
+    block = 1024
+    nblk = (n + block - 1) // block
+    seqs = np.random.SeedSequence(seed).spawn(nblk)
+    noise = np.empty((n, n), dtype=np.float32)
+
+    def rows(r0, r1):
+        rng = np.random.default_rng(seqs[r0 // block])
+        noise[r0:r1] = rng.standard_normal((r1 - r0, n), dtype=np.float32)
+
+    _parallel_rows(n, block, rows)
     r = int(np.ceil(truncate * sigma_px))
     t = np.arange(-r, r + 1, dtype=np.float64)
     g = np.exp(-0.5 * (t / sigma_px) ** 2)
@@ -95,10 +121,11 @@ def smooth_noise(n, seed, sigma_px=8.0, std=0.02, truncate=4.0):
     # the kernel is real and even about 0, so its spectrum is real
     kspec = np.fft.rfft(kern).real
     kfull = np.fft.fft(kern).real
-    spec = sfft.rfft2(noise, workers=-1)
+    spec = sfft.rfft2(noise, workers=_threads())
+    del noise
     spec *= kspec[None, :].astype(np.float32)
     spec *= kfull[:, None].astype(np.float32)
-    out = sfft.irfft2(spec, s=(n, n), workers=-1).astype(np.float32)
+    out = sfft.irfft2(spec, s=(n, n), workers=_threads()).astype(np.float32, copy=False)
     del spec
     out *= np.float32(std / float(out.std(dtype=np.float64)))
     return out

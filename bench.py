@@ -80,6 +80,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="large", choices=["large", "mid", "small"])
+    ap.add_argument("--lambdas", type=int, default=0,
+                    help="profiling runs only: keep the first K wavelengths")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="profiling runs only: first run a plain 4 GiB device copy, the "
+                         "reference for HBM byte counters")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -93,6 +98,9 @@ def main():
     from paper_2505_22313_amd import workloads as wl
 
     p = wl.problem(args.workload)
+    if args.lambdas:
+        for key in ("lams", "n_index", "weights"):
+            p[key] = p[key][:args.lambdas]
     n, m, k = p["n"], p["m"], len(p["lams"])
     log(f"workload {args.workload}: N={n} M={m} K={k}; generating heights on the host")
     t0 = time.time()
@@ -100,6 +108,13 @@ def main():
     log(f"heights ready in {time.time() - t0:.1f} s")
 
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        src = torch.ones(1 << 30, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 4 GiB read + 4 GiB written")
+        del src, dst
     ctx = api.default_context(0)
     prob = api.Problem.from_dict(p)
     hd = torch.from_numpy(h).cuda()

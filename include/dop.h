@@ -107,7 +107,8 @@ dop_status dop_context_destroy(dop_context *ctx);
 
 /*
  * Workspace bytes an operation needs for `prob` (op = DOP_OP_*): one M x M
- * c64 field (8 M^2 bytes).  Pure host call.
+ * c64 field stored with a row pitch of M + 16 elements (8 M (M + 16) bytes).
+ * Pure host call.
  */
 dop_status dop_workspace_size(const dop_context *ctx, const dop_problem *prob,
                               int op, size_t *bytes);

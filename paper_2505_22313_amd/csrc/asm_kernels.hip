@@ -224,26 +224,32 @@ struct LastRegs {
 // ld(j, b), or the register block), every later stage from LDS.  The last
 // stage writes natural-order results to SNK (LDS, a store functor
 // st(j, b, v), or the register block).  All threads of the block must call.
-template <class G, bool INV, bool REV, int S, int SRC, int SNK, class LoadF, class StoreF,
+template <class G, bool INV, bool REV, int S, int SRC, int SNK, int THI, class LoadF, class StoreF,
           int PERR, int RR>
-DEV void stages(float2 *lds, const float2 *__restrict__ tw, const LoadF &ld, const StoreF &st,
-                float2 (&regs)[PERR][RR]) {
+DEV void stages(float2 *lds, const float2 *twl, const LoadF &ld, const StoreF &st,
+                float2 (&regs)[PERR][RR], const int tid, const int nb_act) {
   constexpr int NSTG = num_stages(G::L);
   constexpr int R = stage_radix(G::L, S, REV);
   constexpr int NS = stage_ns(G::L, S, REV);
   constexpr bool FIRST = (S == 0), LAST = (S == NSTG - 1);
   using SS = StageShape<G, R>;
   constexpr int LR = SS::LR, PER = SS::PER, ITEMS = SS::ITEMS;
-  constexpr int TWSH = kTwLog - ilog2c(NS * R);
-  const int tid = threadIdx.x;
+  static_assert(NS * R <= THI, "twiddle table too small");
+  constexpr int TWMUL = THI / (NS * R);  // omega_{NS R}^e = twl[e * TWMUL]
 
   float2 v[PER][R];
+  // an item is live if it exists and its batch column is below nb_act (the
+  // columns at or beyond nb_act are known to be zero, or are not needed)
+  auto live = [&](int it, int &j, int &b) {
+    if (!(SS::EXACT || it < ITEMS)) return false;
+    decode_item<G, R>(it, j, b);
+    return b < nb_act;
+  };
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int it = tid + i * G::T;
-    if (SS::EXACT || it < ITEMS) {
-      int j, b;
-      decode_item<G, R>(it, j, b);
+    int j, b;
+    if (live(it, j, b)) {
       if constexpr (FIRST && SRC == SRC_REG) {
         static_assert(PERR == PER && RR == R, "register hand-off shape");
 #pragma unroll
@@ -261,14 +267,13 @@ DEV void stages(float2 *lds, const float2 *__restrict__ tw, const LoadF &ld, con
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int it = tid + i * G::T;
-    if (SS::EXACT || it < ITEMS) {
+    int j, b;
+    if (live(it, j, b)) {
       if constexpr (!FIRST) {
-        int j, b;
-        decode_item<G, R>(it, j, b);
         const int k = j & (NS - 1);
 #pragma unroll
         for (int t = 1; t < R; ++t) {
-          const float2 w = tw[(t * k) << TWSH];
+          const float2 w = twl[(t * k) * TWMUL];
           v[i][t] = INV ? cmulc(v[i][t], w) : cmul(v[i][t], w);
         }
       }
@@ -281,9 +286,8 @@ DEV void stages(float2 *lds, const float2 *__restrict__ tw, const LoadF &ld, con
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int it = tid + i * G::T;
-      if (SS::EXACT || it < ITEMS) {
-        int j, b;
-        decode_item<G, R>(it, j, b);
+      int j, b;
+      if (live(it, j, b)) {
 #pragma unroll
         for (int t = 0; t < R; ++t) {
           if constexpr (SNK == SNK_REG) {
@@ -303,9 +307,8 @@ DEV void stages(float2 *lds, const float2 *__restrict__ tw, const LoadF &ld, con
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int it = tid + i * G::T;
-      if (SS::EXACT || it < ITEMS) {
-        int j, b;
-        decode_item<G, R>(it, j, b);
+      int j, b;
+      if (live(it, j, b)) {
         const int k = j & (NS - 1);
         const int base = (j - k) * R + k;
 #pragma unroll
@@ -313,15 +316,26 @@ DEV void stages(float2 *lds, const float2 *__restrict__ tw, const LoadF &ld, con
       }
     }
     __syncthreads();
-    stages<G, INV, REV, S + 1, SRC_LDS, SNK>(lds, tw, ld, st, regs);
+    stages<G, INV, REV, S + 1, SRC_LDS, SNK, THI>(lds, twl, ld, st, regs, tid, nb_act);
   }
 }
 
-template <class G, bool INV, bool REV, int SRC, int SNK, class LoadF, class StoreF, int PERR,
-          int RR>
-DEV void dft_tile(float2 *lds, const float2 *__restrict__ tw, const LoadF &ld, const StoreF &st,
-                  float2 (&regs)[PERR][RR]) {
-  stages<G, INV, REV, 0, SRC, SNK>(lds, tw, ld, st, regs);
+// L-point DFT of every batch column of a tile; twl is the LDS table
+// omega_THI^i, i < THI (THI a multiple of L).
+template <class G, bool INV, bool REV, int SRC, int SNK, int THI, class LoadF, class StoreF,
+          int PERR, int RR>
+DEV void dft_tile(float2 *lds, const float2 *twl, const LoadF &ld, const StoreF &st,
+                  float2 (&regs)[PERR][RR], const int tid, const int nb_act = G::NB) {
+  stages<G, INV, REV, 0, SRC, SNK, THI>(lds, twl, ld, st, regs, tid, nb_act);
+}
+
+// Thread index re-read in every tile iteration through an empty asm
+// statement, so per-thread LDS addresses are recomputed inside the tile loop
+// instead of being hoisted out of it and spilled.
+DEV int loop_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
 }
 
 struct NoLoad {
@@ -343,9 +357,13 @@ __host__ __device__ constexpr int plan_ay(int lm) {
 }
 __host__ __device__ constexpr int threads_for(int pts) { return cmin(512, cmax(64, pts / 16)); }
 
+// Two 512-thread blocks per CU = 4 waves per SIMD: caps registers at 128.
+#define DOP_KERNEL(T) __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4)))
+
 template <int LOGM>
 struct Plan {
   static constexpr int M = 1 << LOGM;
+  static constexpr size_t PITCH = (size_t)M + kRowPad;  // workspace row pitch
   static constexpr int BX = 1 << plan_bx(LOGM);
   static constexpr int AX = M / BX;
   static constexpr int AY = 1 << plan_ay(LOGM);
@@ -355,20 +373,79 @@ struct Plan {
   static constexpr int TA = threads_for(AX * RA);
   static constexpr int TB = threads_for(BX * AY);
   static constexpr int TC = threads_for(BY * RC);
+  // Twiddles in LDS: omega_M^q = HI[q / S] * LO[q % S] with HI[i] = omega_M^(i S)
+  // (= omega_THI^i, which also serves every inner DFT length L <= THI) and
+  // LO[i] = omega_M^i.
+  static constexpr int THI = M < 1024 ? M : 1024;
+  static constexpr int S = M / THI;
+  static constexpr int LOGS = ilog2c(S);
 };
+
+template <int LOGM>
+struct TwLds {
+  float2 hi[Plan<LOGM>::THI];
+  float2 lo[Plan<LOGM>::S];
+};
+
+// Copy this plan's twiddles from the FP64-generated global table into LDS.
+template <int LOGM, int T>
+DEV void tw_fill(TwLds<LOGM> &t, const float2 *__restrict__ g) {
+  using P = Plan<LOGM>;
+  for (int i = threadIdx.x; i < P::THI; i += T) t.hi[i] = g[(i * P::S) << (kTwLog - LOGM)];
+  for (int i = threadIdx.x; i < P::S; i += T) t.lo[i] = g[i << (kTwLog - LOGM)];
+}
+
+// omega_M^q (forward sign).
+template <int LOGM>
+DEV float2 tw_q(const TwLds<LOGM> &t, int q) {
+  using P = Plan<LOGM>;
+  q &= P::M - 1;
+  if constexpr (P::S == 1) {
+    return t.hi[q];
+  } else {
+    return cmul(t.hi[q >> P::LOGS], t.lo[q & (P::S - 1)]);
+  }
+}
+
+// Tiles per launch are walked by a grid of resident blocks.  Blocks are
+// handed to the eight XCDs round-robin, so tile ids are permuted within each
+// run of 64 to give every XCD eight consecutive tiles at a time (neighbouring
+// tiles share cache lines and DRAM pages).
+__host__ __device__ constexpr int kMaxBlocks = 4096;
+DEV int xcd_tile(int p, int ntiles) {
+  if (p >= (ntiles & ~63)) return p;
+  return (p & ~63) | ((p & 7) << 3) | ((p >> 3) & 7);
+}
 
 // ---------------------------------------------------------------------------
 // Element-wise physics.
 // ---------------------------------------------------------------------------
 
+// exp(i 2 pi f) for f in [-1/2, 1/2] turn: the hardware sine and cosine take
+// their argument in turns (max abs error 1.3e-7 over [-1/2, 1/2], measured
+// against FP64 on gfx950).
+DEV float2 cis_turns(float f) {
+  return make_float2(__builtin_amdgcn_cosf(f), __builtin_amdgcn_sinf(f));
+}
+
 // exp(i 2 pi q), q = turns_per_h * h formed in FP64 and reduced to
 // [-1/2, 1/2] turn before the cast to FP32 (Eq. 1-2).
 DEV float2 doe_phase(float hv, double turns_per_h) {
   const double q = turns_per_h * (double)hv;
-  const double fr = q - rint(q);
-  float s, c;
-  sincospif((float)(2.0 * fr), &s, &c);
-  return make_float2(c, s);
+  return cis_turns((float)(q - rint(q)));
+}
+
+// sqrt(q) for q in (0, 1] in FP64: FP32 reciprocal-square-root seed, one
+// Goldschmidt iteration (relative error ~1e-14), then a Newton correction of
+// the root (about 1 ulp).
+DEV double sqrt_unit(double q) {
+  const double r = (double)__builtin_amdgcn_rsqf((float)q);
+  double g = q * r, h = 0.5 * r;
+  const double e = fma(-g, h, 0.5);
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  const double d = fma(-g, g, q);
+  return fma(d, h, g);
 }
 
 // (lambda * f)^2 for DFT bin k of M, f = k_signed / (M dx), each product
@@ -383,174 +460,218 @@ DEV double lam_f_sq(int k, int m, const KParams &p) {
 
 // H(ky, kx) / M^2 (conjugated when p.adjoint): zero unless
 // s = a2y + a2x < 1; else exp(i 2 pi (z/lambda) sqrt(1 - s)) with the
-// argument formed and reduced mod one turn in FP64.
+// argument formed and reduced mod one turn in FP64.  Branch-free: evanescent
+// bins evaluate a dummy argument and are scaled by zero.
 DEV float2 transfer(double a2y, double a2x, const KParams &p) {
 #pragma clang fp contract(off)
   const double s = a2y + a2x;
-  if (!(s < 1.0)) return make_float2(0.f, 0.f);
-  const double root = sqrt(1.0 - s);
-  const double t = p.zl * root;
-  const double fr = t - rint(t);
-  float sn, cs;
-  sincospif((float)(2.0 * fr), &sn, &cs);
-  if (p.adjoint) sn = -sn;
-  return make_float2(cs * p.inv_m2, sn * p.inv_m2);
-}
-
-DEV float2 twiddle(const float2 *__restrict__ tw, int q, int logm) {
-  return tw[(q & ((1 << logm) - 1)) << (kTwLog - logm)];
+  const bool prop = s < 1.0;
+  const double t = p.zl * sqrt_unit(prop ? 1.0 - s : 1.0);
+  const float2 w = cis_turns((float)(t - rint(t)));
+  const float re = prop ? p.inv_m2 : 0.f;
+  const float im = prop ? (p.adjoint ? -p.inv_m2 : p.inv_m2) : 0.f;
+  return make_float2(w.x * re, w.y * im);
 }
 
 // ---------------------------------------------------------------------------
 // Pass A: DFT over xa for the N input rows, input formed on the fly.
-// Block = one row y and a run of RA consecutive xb.
+// Tile = one row y and a run of RA consecutive xb.
 // ---------------------------------------------------------------------------
 template <int LOGM>
-__global__ __launch_bounds__(Plan<LOGM>::TA) void k_pass_a_fwd(KParams p) {
+DOP_KERNEL(Plan<LOGM>::TA) void k_pass_a_fwd(KParams p) {
   using P = Plan<LOGM>;
-  constexpr int AX = P::AX, BX = P::BX, RA = P::RA, M = P::M;
-  using G = Geo<AX, RA, RA + 1, 1, P::TA, false>;
-  __shared__ float2 lds[AX * (RA + 1)];
+  constexpr int AX = P::AX, BX = P::BX, RA = P::RA, M = P::M, T = P::TA;
+  using G = Geo<AX, RA, RA, 1, T, false>;
+  __shared__ float2 lds[AX * RA];
+  __shared__ TwLds<LOGM> tw;
+  tw_fill<LOGM, T>(tw, p.tw);
   constexpr int RUNS = BX / RA;
-  const int y = blockIdx.x / RUNS;
-  const int xb0 = (blockIdx.x % RUNS) * RA;
+  const int ntiles = p.nrows_in * RUNS;
   const int n = p.n;
-  const size_t rowin = (size_t)y * n;
-
-  auto ld = [&](int xa, int b) -> float2 {
-    const int x = BX * xa + xb0 + b;
-    if (x >= n) return make_float2(0.f, 0.f);
-    const size_t idx = rowin + x;
-    if (p.in_mode == IN_PHASE) {
-      float2 e = doe_phase(p.h[idx], p.phase_turns);
-      if (p.amp) e = cscale(e, p.amp[idx]);
-      return e;
-    } else if (p.in_mode == IN_FIELD) {
-      return p.u_in[idx];
-    } else {
-      return cscale(p.saved_in[idx], p.two_wk * p.gpsf[idx]);
-    }
-  };
-  float2 *out = p.ws + (size_t)y * M;
-  auto st = [&](int kxa, int b, float2 v) {
-    const int xb = xb0 + b;
-    out[BX * kxa + xb] = cmul(v, twiddle(p.tw, xb * kxa, LOGM));
-  };
   float2 dummy[1][1];
-  dft_tile<G, false, false, SRC_FN, SNK_FN>(lds, p.tw, ld, st, dummy);
+  for (int pt = blockIdx.x; pt < ntiles; pt += gridDim.x) {
+    const int tid = loop_tid();
+    const int tile = xcd_tile(pt, ntiles);
+    const int y = tile / RUNS;
+    const int xb0 = (tile % RUNS) * RA;
+    const size_t rowin = (size_t)y * n;
+    __syncthreads();
+    auto ld = [&](int xa, int b) -> float2 {
+      const int x = BX * xa + xb0 + b;
+      if (x >= n) return make_float2(0.f, 0.f);
+      const size_t idx = rowin + x;
+      if (p.in_mode == IN_PHASE) {
+        float2 e = doe_phase(p.h[idx], p.phase_turns);
+        if (p.amp) e = cscale(e, p.amp[idx]);
+        return e;
+      } else if (p.in_mode == IN_FIELD) {
+        return p.u_in[idx];
+      } else {
+        return cscale(p.saved_in[idx], p.two_wk * p.gpsf[idx]);
+      }
+    };
+    float2 *out = p.ws + (size_t)y * P::PITCH;
+    auto st = [&](int kxa, int b, float2 v) {
+      const int xb = xb0 + b;
+      out[BX * kxa + xb] = cmul(v, tw_q<LOGM>(tw, xb * kxa));
+    };
+    dft_tile<G, false, false, SRC_FN, SNK_FN, P::THI>(lds, tw.hi, ld, st, dummy, tid);
+  }
 }
 
 // ---------------------------------------------------------------------------
-// Pass B: DFT over xb then over ya on a BX x AY tile (block = (kxa, yb)).
+// Pass B: DFT over xb then over ya on a BX x AY tile (tile = (kxa, yb)).
+// Rows are moved between HBM and LDS as 16-byte (two-element) vectors.
 // ---------------------------------------------------------------------------
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+DEV f4v ld_pair(const float2 *p) { return *reinterpret_cast<const f4v *>(p); }
+DEV void st_pair(float2 *p, float2 a, float2 b) {
+  *reinterpret_cast<f4v *>(p) = f4v{a.x, a.y, b.x, b.y};
+}
+
 template <int LOGM>
-__global__ __launch_bounds__(Plan<LOGM>::TB) void k_pass_b_fwd(KParams p) {
+DOP_KERNEL(Plan<LOGM>::TB) void k_pass_b_fwd(KParams p) {
   using P = Plan<LOGM>;
   constexpr int AX = P::AX, BX = P::BX, AY = P::AY, BY = P::BY, M = P::M, T = P::TB;
-  constexpr int SR = BX + 1;
+  constexpr int SR = BX + 1;  // odd row stride: conflict-free for both DFT directions
+  constexpr int HB = BX / 2;  // 16-byte pairs per row segment
   __shared__ float2 lds[AY * SR];
-  const int kxa = blockIdx.x % AX;
-  const int yb = blockIdx.x / AX;
-  const float2 *__restrict__ ws = p.ws;
-  const size_t col0 = (size_t)BX * kxa;
-
-  for (int e = threadIdx.x; e < AY * BX; e += T) {
-    const int ya = e / BX, xb = e % BX;
-    const int y = BY * ya + yb;
-    lds[ya * SR + xb] = (y < p.nrows_in) ? ws[(size_t)y * M + col0 + xb] : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-
+  __shared__ TwLds<LOGM> tw;
+  __shared__ float2 rowtw[AY];
+  tw_fill<LOGM, T>(tw, p.tw);
+  constexpr int NT = AX * BY;
   float2 dummy[1][1];
-  using GX = Geo<BX, AY, 1, SR, T, true>;
-  dft_tile<GX, false, false, SRC_LDS, SNK_LDS>(lds, p.tw, NoLoad{}, NoStore{}, dummy);
-
-  float2 *wsw = p.ws;
-  auto st = [&](int kya, int kxb, float2 v) {
-    wsw[(size_t)(BY * kya + yb) * M + col0 + kxb] = cmul(v, twiddle(p.tw, yb * kya, LOGM));
-  };
-  using GY = Geo<AY, BX, SR, 1, T, false>;
-  dft_tile<GY, false, false, SRC_LDS, SNK_FN>(lds, p.tw, NoLoad{}, st, dummy);
+  for (int pt = blockIdx.x; pt < NT; pt += gridDim.x) {
+    const int tid = loop_tid();
+    const int tile = xcd_tile(pt, NT);
+    const int kxa = tile % AX;
+    const int yb = tile / AX;
+    const size_t col0 = (size_t)BX * kxa;
+    // rows ya with BY*ya + yb >= nrows_in hold zeros: not read, x-DFT skipped
+    const int nz = p.nrows_in > yb ? cmin(AY, (p.nrows_in - yb + BY - 1) / BY) : 0;
+    __syncthreads();
+    for (int r = tid; r < AY; r += T) rowtw[r] = tw_q<LOGM>(tw, yb * r);  // omega_M^(yb kya)
+    for (int e = tid; e < AY * HB; e += T) {
+      const int ya = e / HB, c = e % HB;
+      f4v v = {0.f, 0.f, 0.f, 0.f};
+      if (ya < nz) v = ld_pair(p.ws + (size_t)(BY * ya + yb) * P::PITCH + col0 + 2 * c);
+      lds[ya * SR + 2 * c] = make_float2(v.x, v.y);
+      lds[ya * SR + 2 * c + 1] = make_float2(v.z, v.w);
+    }
+    __syncthreads();
+    using GX = Geo<BX, AY, 1, SR, T, false>;
+    dft_tile<GX, false, false, SRC_LDS, SNK_LDS, P::THI>(lds, tw.hi, NoLoad{}, NoStore{}, dummy, tid,
+                                                        nz);
+    using GY = Geo<AY, BX, SR, 1, T, false>;
+    dft_tile<GY, false, false, SRC_LDS, SNK_LDS, P::THI>(lds, tw.hi, NoLoad{}, NoStore{}, dummy, tid);
+    for (int e = tid; e < AY * HB; e += T) {
+      const int kya = e / HB, c = e % HB;
+      const float2 w = rowtw[kya];
+      st_pair(p.ws + (size_t)(BY * kya + yb) * P::PITCH + col0 + 2 * c, cmul(lds[kya * SR + 2 * c], w),
+              cmul(lds[kya * SR + 2 * c + 1], w));
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
-// Pass C: DFT over yb, times H, inverse DFT over yb (block = (kya, run of RC
+// Pass C: DFT over yb, times H, inverse DFT over yb (tile = (kya, run of RC
 // columns)).
 // ---------------------------------------------------------------------------
 template <int LOGM>
-__global__ __launch_bounds__(Plan<LOGM>::TC) void k_pass_c(KParams p) {
+DOP_KERNEL(Plan<LOGM>::TC) void k_pass_c(KParams p) {
   using P = Plan<LOGM>;
   constexpr int AX = P::AX, BX = P::BX, AY = P::AY, BY = P::BY, M = P::M, RC = P::RC, T = P::TC;
   using G = Geo<BY, RC, RC + 1, 1, T, false>;
   __shared__ float2 lds[BY * (RC + 1)];
+  __shared__ TwLds<LOGM> tw;
+  tw_fill<LOGM, T>(tw, p.tw);
   constexpr int RUNS = M / RC;
-  const int px0 = (blockIdx.x % RUNS) * RC;
-  const int kya = blockIdx.x / RUNS;
-  float2 *base = p.ws + (size_t)(BY * kya) * M + px0;
-
-  auto ld = [&](int yb, int b) -> float2 { return base[(size_t)yb * M + b]; };
-  auto st = [&](int yb, int b, float2 v) { base[(size_t)yb * M + b] = v; };
-
+  constexpr int NT = AY * RUNS;
   using LR_ = LastRegs<G, false>;
-  float2 regs[LR_::PER][LR_::R];
-  dft_tile<G, false, false, SRC_FN, SNK_REG>(lds, p.tw, ld, NoStore{}, regs);
+  for (int pt = blockIdx.x; pt < NT; pt += gridDim.x) {
+    const int tid = loop_tid();
+    const int tile = xcd_tile(pt, NT);
+    const int px0 = (tile % RUNS) * RC;
+    const int kya = tile / RUNS;
+    float2 *base = p.ws + (size_t)(BY * kya) * P::PITCH + px0;
+    __syncthreads();
+    auto ld = [&](int yb, int b) -> float2 { return base[(size_t)yb * P::PITCH + b]; };
+    auto st = [&](int yb, int b, float2 v) { base[(size_t)yb * P::PITCH + b] = v; };
 
-  {
-    constexpr int R = LR_::R;
-    constexpr int LRn = BY / R;
-    using SS = StageShape<G, R>;
+    float2 regs[LR_::PER][LR_::R];
+    dft_tile<G, false, false, SRC_FN, SNK_REG, P::THI>(lds, tw.hi, ld, NoStore{}, regs, tid);
+    {
+      constexpr int R = LR_::R;
+      constexpr int LRn = BY / R;
+      using SS = StageShape<G, R>;
 #pragma unroll
-    for (int i = 0; i < LR_::PER; ++i) {
-      const int it = threadIdx.x + i * T;
-      if (SS::EXACT || it < SS::ITEMS) {
-        int j, b;
-        decode_item<G, R>(it, j, b);
-        const int px = px0 + b;
-        const int kx = (px / BX) + AX * (px % BX);
-        const double a2x = lam_f_sq(kx, M, p);
+      for (int i = 0; i < LR_::PER; ++i) {
+        const int it = tid + i * T;
+        if (SS::EXACT || it < SS::ITEMS) {
+          int j, b;
+          decode_item<G, R>(it, j, b);
+          const int px = px0 + b;
+          const int kx = (px / BX) + AX * (px % BX);
+          const double a2x = lam_f_sq(kx, M, p);
 #pragma unroll
-        for (int t = 0; t < R; ++t) {
-          const int kyb = j + t * LRn;
-          const int ky = kya + AY * kyb;
-          regs[i][t] = cmul(regs[i][t], transfer(lam_f_sq(ky, M, p), a2x, p));
+          for (int t = 0; t < R; ++t) {
+            const int kyb = j + t * LRn;
+            const int ky = kya + AY * kyb;
+            regs[i][t] = cmul(regs[i][t], transfer(lam_f_sq(ky, M, p), a2x, p));
+          }
         }
       }
     }
+    dft_tile<G, true, true, SRC_REG, SNK_FN, P::THI>(lds, tw.hi, NoLoad{}, st, regs, tid);
   }
-
-  dft_tile<G, true, true, SRC_REG, SNK_FN>(lds, p.tw, NoLoad{}, st, regs);
 }
 
 // ---------------------------------------------------------------------------
-// Pass B': inverse DFT over kya then over kxb (block = (kxa, yb)); writes the
+// Pass B': inverse DFT over kya then over kxb (tile = (kxa, yb)); writes the
 // rows y < nrows_out.
 // ---------------------------------------------------------------------------
 template <int LOGM>
-__global__ __launch_bounds__(Plan<LOGM>::TB) void k_pass_b_inv(KParams p) {
+DOP_KERNEL(Plan<LOGM>::TB) void k_pass_b_inv(KParams p) {
   using P = Plan<LOGM>;
   constexpr int AX = P::AX, BX = P::BX, AY = P::AY, BY = P::BY, M = P::M, T = P::TB;
   constexpr int SR = BX + 1;
+  constexpr int HB = BX / 2;
   __shared__ float2 lds[AY * SR];
-  const int kxa = blockIdx.x % AX;
-  const int yb = blockIdx.x / AX;
-  const size_t col0 = (size_t)BX * kxa;
-  const float2 *__restrict__ ws = p.ws;
-
-  auto ld = [&](int kya, int kxb) -> float2 {
-    const float2 v = ws[(size_t)(BY * kya + yb) * M + col0 + kxb];
-    return cmulc(v, twiddle(p.tw, yb * kya, LOGM));
-  };
+  __shared__ TwLds<LOGM> tw;
+  __shared__ float2 rowtw[AY];
+  tw_fill<LOGM, T>(tw, p.tw);
+  constexpr int NT = AX * BY;
   float2 dummy[1][1];
-  using GY = Geo<AY, BX, SR, 1, T, false>;
-  dft_tile<GY, true, false, SRC_FN, SNK_LDS>(lds, p.tw, ld, NoStore{}, dummy);
-  using GX = Geo<BX, AY, 1, SR, T, true>;
-  dft_tile<GX, true, false, SRC_LDS, SNK_LDS>(lds, p.tw, NoLoad{}, NoStore{}, dummy);
-
-  float2 *wsw = p.ws;
-  for (int e = threadIdx.x; e < AY * BX; e += T) {
-    const int ya = e / BX, xb = e % BX;
-    const int y = BY * ya + yb;
-    if (y < p.nrows_out) wsw[(size_t)y * M + col0 + xb] = lds[ya * SR + xb];
+  for (int pt = blockIdx.x; pt < NT; pt += gridDim.x) {
+    const int tid = loop_tid();
+    const int tile = xcd_tile(pt, NT);
+    const int kxa = tile % AX;
+    const int yb = tile / AX;
+    const size_t col0 = (size_t)BX * kxa;
+    // only the rows ya with BY*ya + yb < nrows_out are needed
+    const int nz = p.nrows_out > yb ? cmin(AY, (p.nrows_out - yb + BY - 1) / BY) : 0;
+    __syncthreads();
+    for (int r = tid; r < AY; r += T) rowtw[r] = tw_q<LOGM>(tw, yb * r);
+    __syncthreads();
+    for (int e = tid; e < AY * HB; e += T) {
+      const int kya = e / HB, c = e % HB;
+      const f4v v = ld_pair(p.ws + (size_t)(BY * kya + yb) * P::PITCH + col0 + 2 * c);
+      const float2 w = rowtw[kya];
+      lds[kya * SR + 2 * c] = cmulc(make_float2(v.x, v.y), w);
+      lds[kya * SR + 2 * c + 1] = cmulc(make_float2(v.z, v.w), w);
+    }
+    __syncthreads();
+    using GY = Geo<AY, BX, SR, 1, T, false>;
+    dft_tile<GY, true, false, SRC_LDS, SNK_LDS, P::THI>(lds, tw.hi, NoLoad{}, NoStore{}, dummy, tid);
+    using GX = Geo<BX, AY, 1, SR, T, false>;
+    dft_tile<GX, true, false, SRC_LDS, SNK_LDS, P::THI>(lds, tw.hi, NoLoad{}, NoStore{}, dummy, tid,
+                                                       nz);
+    for (int e = tid; e < nz * HB; e += T) {
+      const int ya = e / HB, c = e % HB;
+      st_pair(p.ws + (size_t)(BY * ya + yb) * P::PITCH + col0 + 2 * c, lds[ya * SR + 2 * c],
+              lds[ya * SR + 2 * c + 1]);
+    }
   }
 }
 
@@ -559,46 +680,53 @@ __global__ __launch_bounds__(Plan<LOGM>::TB) void k_pass_b_inv(KParams p) {
 // stage: PSF accumulation (Eq. 4), field, or height gradient.
 // ---------------------------------------------------------------------------
 template <int LOGM>
-__global__ __launch_bounds__(Plan<LOGM>::TA) void k_pass_a_inv(KParams p) {
+DOP_KERNEL(Plan<LOGM>::TA) void k_pass_a_inv(KParams p) {
   using P = Plan<LOGM>;
-  constexpr int AX = P::AX, BX = P::BX, RA = P::RA, M = P::M;
-  using G = Geo<AX, RA, RA + 1, 1, P::TA, false>;
-  __shared__ float2 lds[AX * (RA + 1)];
+  constexpr int AX = P::AX, BX = P::BX, RA = P::RA, M = P::M, T = P::TA;
+  using G = Geo<AX, RA, RA, 1, T, false>;
+  __shared__ float2 lds[AX * RA];
+  __shared__ TwLds<LOGM> tw;
+  tw_fill<LOGM, T>(tw, p.tw);
   constexpr int RUNS = BX / RA;
-  const int y = blockIdx.x / RUNS;
-  const int xb0 = (blockIdx.x % RUNS) * RA;
+  const int ntiles = p.nrows_out * RUNS;
   const int n = p.n;
-  const float2 *__restrict__ row = p.ws + (size_t)y * M;
-
-  auto ld = [&](int kxa, int b) -> float2 {
-    const int xb = xb0 + b;
-    return cmulc(row[BX * kxa + xb], twiddle(p.tw, xb * kxa, LOGM));
-  };
-  auto st = [&](int xa, int b, float2 u) {
-    const int x = BX * xa + xb0 + b;
-    size_t idx;
-    if (p.full) {
-      const int yo = (y + p.p0) & (M - 1), xo = (x + p.p0) & (M - 1);
-      idx = (size_t)yo * M + xo;
-    } else {
-      if (x >= n) return;
-      idx = (size_t)y * n + x;
-    }
-    if (p.out_mode == OUT_PSF) {
-      const float v = p.wk * (u.x * u.x + u.y * u.y);
-      p.psf[idx] = p.first ? v : p.psf[idx] + v;
-      if (p.saved_out) p.saved_out[idx] = u;
-    } else if (p.out_mode == OUT_FIELD) {
-      p.u_out[idx] = u;
-    } else {
-      float2 e = doe_phase(p.h[idx], p.phase_turns);
-      if (p.amp) e = cscale(e, p.amp[idx]);
-      const float v = p.ck * (u.y * e.x - u.x * e.y);  // c_k Im(g_E conj(E))
-      p.grad_h[idx] = p.first ? v : p.grad_h[idx] + v;
-    }
-  };
   float2 dummy[1][1];
-  dft_tile<G, true, false, SRC_FN, SNK_FN>(lds, p.tw, ld, st, dummy);
+  for (int pt = blockIdx.x; pt < ntiles; pt += gridDim.x) {
+    const int tid = loop_tid();
+    const int tile = xcd_tile(pt, ntiles);
+    const int y = tile / RUNS;
+    const int xb0 = (tile % RUNS) * RA;
+    const float2 *__restrict__ row = p.ws + (size_t)y * P::PITCH;
+    __syncthreads();
+    auto ld = [&](int kxa, int b) -> float2 {
+      const int xb = xb0 + b;
+      return cmulc(row[BX * kxa + xb], tw_q<LOGM>(tw, xb * kxa));
+    };
+    auto st = [&](int xa, int b, float2 u) {
+      const int x = BX * xa + xb0 + b;
+      size_t idx;
+      if (p.full) {
+        const int yo = (y + p.p0) & (M - 1), xo = (x + p.p0) & (M - 1);
+        idx = (size_t)yo * M + xo;
+      } else {
+        if (x >= n) return;
+        idx = (size_t)y * n + x;
+      }
+      if (p.out_mode == OUT_PSF) {
+        const float v = p.wk * (u.x * u.x + u.y * u.y);
+        p.psf[idx] = p.first ? v : p.psf[idx] + v;
+        if (p.saved_out) p.saved_out[idx] = u;
+      } else if (p.out_mode == OUT_FIELD) {
+        p.u_out[idx] = u;
+      } else {
+        float2 e = doe_phase(p.h[idx], p.phase_turns);
+        if (p.amp) e = cscale(e, p.amp[idx]);
+        const float v = p.ck * (u.y * e.x - u.x * e.y);  // c_k Im(g_E conj(E))
+        p.grad_h[idx] = p.first ? v : p.grad_h[idx] + v;
+      }
+    };
+    dft_tile<G, true, false, SRC_FN, SNK_FN, P::THI>(lds, tw.hi, ld, st, dummy, tid);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -611,10 +739,13 @@ static inline void mark(hipEvent_t *ev, int i, hipStream_t s) {
 template <int LOGM>
 static hipError_t launch_impl(const KParams &p, hipStream_t s, hipEvent_t *ev) {
   using P = Plan<LOGM>;
-  const unsigned ga = (unsigned)p.nrows_in * (P::BX / P::RA);
-  const unsigned gb = (unsigned)(P::AX * P::BY);
-  const unsigned gc = (unsigned)(P::AY * (P::M / P::RC));
-  const unsigned gai = (unsigned)p.nrows_out * (P::BX / P::RA);
+  auto grid = [](long long tiles) {
+    return (unsigned)(tiles < kMaxBlocks ? tiles : kMaxBlocks);
+  };
+  const unsigned ga = grid((long long)p.nrows_in * (P::BX / P::RA));
+  const unsigned gb = grid((long long)P::AX * P::BY);
+  const unsigned gc = grid((long long)P::AY * (P::M / P::RC));
+  const unsigned gai = grid((long long)p.nrows_out * (P::BX / P::RA));
   mark(ev, 0, s);
   hipLaunchKernelGGL(k_pass_a_fwd<LOGM>, dim3(ga), dim3(P::TA), 0, s, p);
   mark(ev, 1, s);

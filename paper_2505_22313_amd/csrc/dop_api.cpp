@@ -86,7 +86,7 @@ dop_status validate_problem(const dop_problem *prob) {
 }
 
 size_t workspace_bytes(const dop_problem *prob) {
-  return (size_t)prob->m * (size_t)prob->m * sizeof(float2);
+  return (size_t)prob->m * ((size_t)prob->m + kRowPad) * sizeof(float2);
 }
 
 // Fill the per-wavelength kernel parameters shared by every operation.

@@ -12,6 +12,11 @@ namespace dop {
 constexpr int kTwLog = 16;
 constexpr int kTwN = 1 << kTwLog;
 
+// Row pitch of the M x M workspace, in elements: M + kRowPad.  The pad keeps
+// rows that are a power of two apart from landing on the same HBM channels
+// (column passes read hundreds of rows at one column offset).
+constexpr int kRowPad = 16;
+
 // Pass-A input modes.
 enum InMode : int {
   IN_PHASE = 0,  // E = amp * exp(i 2 pi (n-1)/lambda h)        (Eq. 1-2)

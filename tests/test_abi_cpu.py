@@ -1,0 +1,246 @@
+"""C-ABI contract of libdop on the CPU (no GPU needed, no compute calls).
+
+* the library loads and exports every function include/dop.h declares;
+* problem validation returns the documented status codes;
+* entry points reject bad handles before touching a device;
+* the serving scheduler (FIFO admission by arena budget, slot accounting,
+  cancellation, timeouts, latency statistics) driven by its host-side mock
+  executor.
+"""
+
+import ctypes
+import time
+
+import numpy as np
+import pytest
+
+from paper_2505_22313_amd import _lib as L
+from paper_2505_22313_amd import api
+
+
+def lib():
+    return L.lib()
+
+
+def test_exports_every_header_function():
+    names = L.header_functions()
+    assert len(names) >= 17
+    handle = lib()
+    for name in names:
+        assert hasattr(handle, name), name
+        assert getattr(handle, name) is not None
+
+
+def test_status_strings():
+    for code, name in [(0, "DOP_OK"), (1, "DOP_NOT_READY"), (-1, "DOP_ERR_INVALID_ARG"),
+                       (-2, "DOP_ERR_UNSUPPORTED"), (-3, "DOP_ERR_WORKSPACE"),
+                       (-4, "DOP_ERR_DEVICE"), (-5, "DOP_ERR_BUDGET"), (-6, "DOP_ERR_NOT_FOUND"),
+                       (-7, "DOP_ERR_SHUTDOWN"), (-8, "DOP_ERR_TIMEOUT")]:
+        assert L.status_string(code) == name
+    assert L.status_string(42) == "DOP_UNKNOWN_STATUS"
+
+
+def _ws(prob, op=L.DOP_OP_PSF):
+    out = ctypes.c_size_t(0)
+    st = lib().dop_workspace_size(None, prob.ptr(), op, ctypes.byref(out))
+    return st, out.value
+
+
+def good(**kw):
+    d = dict(n=512, m=1024, dx=1.0, z=5000.0, lambdas=[0.55], n_index=[1.46])
+    d.update(kw)
+    return api.Problem(**d)
+
+
+def test_workspace_size_valid():
+    for m in [16, 1024, 65536]:
+        st, b = _ws(good(n=m // 2, m=m))
+        assert st == L.DOP_OK and b == 8 * m * (m + 16)
+    for op in (L.DOP_OP_PROPAGATE, L.DOP_OP_PSF, L.DOP_OP_PSF_BACKWARD):
+        assert _ws(good(), op)[0] == L.DOP_OK
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(m=1000), L.DOP_ERR_UNSUPPORTED),          # not a power of two
+    (dict(m=131072, n=100), L.DOP_ERR_UNSUPPORTED),  # beyond 65536
+    (dict(m=8, n=4), L.DOP_ERR_UNSUPPORTED),         # below the minimum
+    (dict(n=2048), L.DOP_ERR_INVALID_ARG),           # n > m
+    (dict(n=0), L.DOP_ERR_INVALID_ARG),
+    (dict(dx=0.0), L.DOP_ERR_INVALID_ARG),
+    (dict(dx=-1.0), L.DOP_ERR_INVALID_ARG),
+    (dict(dx=float("inf")), L.DOP_ERR_INVALID_ARG),
+    (dict(z=float("nan")), L.DOP_ERR_INVALID_ARG),
+    (dict(lambdas=[0.0], n_index=[1.5]), L.DOP_ERR_INVALID_ARG),
+    (dict(lambdas=[-0.5], n_index=[1.5]), L.DOP_ERR_INVALID_ARG),
+    (dict(lambdas=[0.5], n_index=[float("nan")]), L.DOP_ERR_INVALID_ARG),
+    (dict(z=1e9, lambdas=[1e-4], n_index=[1.5]), L.DOP_ERR_UNSUPPORTED),  # > 1e12 turns
+])
+def test_problem_validation(kw, code):
+    st, _ = _ws(good(**kw))
+    assert st == code, (kw, L.status_string(st), L.last_error())
+    assert L.last_error() != ""
+
+
+def test_validation_struct_fields():
+    p = good()
+    p._c.n_lambda = 0
+    assert _ws(p)[0] == L.DOP_ERR_INVALID_ARG
+    p = good()
+    p._c.n_lambda = 65
+    assert _ws(p)[0] == L.DOP_ERR_INVALID_ARG
+    p = good()
+    p._c.out_mode = 7
+    assert _ws(p)[0] == L.DOP_ERR_INVALID_ARG
+    p = good()
+    p._c.flags = 1
+    assert _ws(p)[0] == L.DOP_ERR_UNSUPPORTED
+    p = good()
+    p._c.lambda_ = None
+    assert _ws(p)[0] == L.DOP_ERR_INVALID_ARG
+    p = good(weights=[float("nan")])
+    assert _ws(p)[0] == L.DOP_ERR_INVALID_ARG
+    out = ctypes.c_size_t(0)
+    assert lib().dop_workspace_size(None, None, 1, ctypes.byref(out)) == L.DOP_ERR_INVALID_ARG
+    assert lib().dop_workspace_size(None, good().ptr(), 9, ctypes.byref(out)) == L.DOP_ERR_INVALID_ARG
+    assert lib().dop_workspace_size(None, good().ptr(), 1, None) == L.DOP_ERR_INVALID_ARG
+    # a successful call clears the thread's last error
+    assert _ws(good())[0] == L.DOP_OK and L.last_error() == ""
+
+
+def test_entry_points_reject_null_context():
+    p = good()
+    v = ctypes.c_void_p(4096)
+    assert lib().dop_psf(None, p.ptr(), v, None, v, None, v, 1 << 30, None) == L.DOP_ERR_INVALID_ARG
+    assert lib().dop_propagate(None, p.ptr(), 0, v, v, v, 1 << 30, None) == L.DOP_ERR_INVALID_ARG
+    assert lib().dop_psf_backward(None, p.ptr(), v, None, v, v, v, v, 1 << 30,
+                                  None) == L.DOP_ERR_INVALID_ARG
+    assert lib().dop_context_destroy(None) == L.DOP_ERR_INVALID_ARG
+    assert lib().dop_profile_enable(None, 1) == L.DOP_ERR_INVALID_ARG
+    assert lib().dop_serve_create(None, v, 1 << 20, 2, ctypes.byref(ctypes.c_void_p())) == \
+        L.DOP_ERR_INVALID_ARG
+
+
+# ---------------------------------------------------------------------------
+# Serving scheduler with the mock executor
+# ---------------------------------------------------------------------------
+
+def req(m, k=1):
+    lams = np.linspace(0.4, 0.7, k) if k > 1 else [0.55]
+    return api.Problem(m // 2, m, 1.0, 1000.0, lams, [1.5] * k)
+
+
+def ws(m):
+    return api.workspace_size(req(m))
+
+
+def test_serve_budget_rejects_impossible_request():
+    srv = api.Server(ws(1024), max_slots=2, mock_us_per_mpix=1.0)
+    try:
+        with pytest.raises(L.DopError) as e:
+            srv.submit(req(2048), 4096, 8192)   # needs ~4x the arena
+        assert e.value.status == L.DOP_ERR_BUDGET
+        t = srv.submit(req(1024), 4096, 8192)  # fits exactly
+        srv.wait(t, 10.0)
+    finally:
+        srv.close()
+
+
+def test_serve_runs_everything_and_reports_latency():
+    srv = api.Server(64 << 20, max_slots=3, mock_us_per_mpix=50.0)
+    try:
+        tickets = [srv.submit(req(m, k), 4096, 8192)
+                   for m, k in [(256, 1), (512, 3), (1024, 2), (256, 5), (512, 1)] * 4]
+        for t in tickets:
+            assert srv.wait(t, 20.0) == L.DOP_OK
+            assert srv.poll(t) == L.DOP_OK
+            assert srv.latency_ms(t) >= 0.0
+        s = srv.stats()
+        assert s["submitted"] == s["completed"] == len(tickets)
+        assert s["failed"] == 0 and s["queued"] == 0 and s["running"] == 0
+        assert 0 < s["arena_peak"] <= 64 << 20
+        assert s["p50_ms"] <= s["p99_ms"]
+    finally:
+        srv.close()
+
+
+def test_serve_memory_limits_concurrency():
+    """Arena for two 1024^2 workspaces, four slots: at most two run at once."""
+    need = ws(1024)
+    srv = api.Server(2 * need, max_slots=4, mock_us_per_mpix=2000.0)  # ~2 ms per request
+    try:
+        tickets = [srv.submit(req(1024), 4096, 8192) for _ in range(6)]
+        peak_running = 0
+        while srv.stats()["completed"] < 6:
+            peak_running = max(peak_running, srv.stats()["running"])
+            time.sleep(0.0005)
+        assert peak_running == 2
+        assert srv.stats()["arena_peak"] == 2 * need
+        for t in tickets:
+            srv.wait(t, 5.0)
+    finally:
+        srv.close()
+
+
+def test_serve_slots_limit_concurrency():
+    srv = api.Server(1 << 30, max_slots=2, mock_us_per_mpix=2000.0)
+    try:
+        tickets = [srv.submit(req(1024), 4096, 8192) for _ in range(5)]
+        peak = 0
+        while srv.stats()["completed"] < 5:
+            peak = max(peak, srv.stats()["running"])
+            time.sleep(0.0005)
+        assert peak == 2
+        for t in tickets:
+            srv.wait(t, 5.0)
+    finally:
+        srv.close()
+
+
+def test_serve_fifo_head_of_line():
+    """A request that does not fit yet holds back the ones behind it, so
+    admission order is submission order."""
+    unit = ws(1024)                    # one 1024^2 workspace
+    srv = api.Server(ws(2048), max_slots=4, mock_us_per_mpix=3000.0)
+    try:
+        a = srv.submit(req(1024, 4), 1, 2)   # 1 unit, ~12.6 ms
+        big = srv.submit(req(2048), 1, 2)    # the whole arena: must wait for a
+        c = srv.submit(req(1024), 1, 2)      # 1 unit: fits now, but queued behind big
+        for t in (a, big, c):
+            srv.wait(t, 10.0)
+        la, lb, lc = srv.latency_ms(a), srv.latency_ms(big), srv.latency_ms(c)
+        assert lb > la            # big started after a finished
+        assert lc > lb            # c was admitted only after big
+    finally:
+        srv.close()
+
+
+def test_serve_shutdown_cancels_queue_and_unknown_ticket():
+    srv = api.Server(ws(1024), max_slots=1, mock_us_per_mpix=5000.0)
+    tickets = [srv.submit(req(1024), 1, 2) for _ in range(4)]
+    assert lib().dop_serve_poll(srv.handle, 999999) == L.DOP_ERR_NOT_FOUND
+    st = lib().dop_serve_wait(srv.handle, tickets[-1], 0.001)
+    assert st == L.DOP_ERR_TIMEOUT
+    srv.close()  # first one finishes, the rest are cancelled
+
+
+def test_serve_cancelled_status_visible_before_destroy():
+    srv = api.Server(ws(1024), max_slots=1, mock_us_per_mpix=5000.0)
+    t1 = srv.submit(req(1024), 1, 2)
+    t2 = srv.submit(req(1024), 1, 2)
+    # destroy in a helper thread would free the server; instead check that the
+    # queued request is reported as not ready, then finish normally
+    assert srv.poll(t2) == L.DOP_NOT_READY
+    srv.wait(t1, 5.0)
+    srv.wait(t2, 5.0)
+    srv.close()
+
+
+def test_serve_rejects_bad_create_args():
+    h = ctypes.c_void_p()
+    assert lib().dop_serve_create_mock(None, 1 << 20, 2, 1.0, ctypes.byref(h)) == L.DOP_ERR_INVALID_ARG
+    assert lib().dop_serve_create_mock(ctypes.c_void_p(256), 1 << 20, 0, 1.0,
+                                       ctypes.byref(h)) == L.DOP_ERR_INVALID_ARG
+    assert lib().dop_serve_create_mock(ctypes.c_void_p(256), 1 << 20, 65, 1.0,
+                                       ctypes.byref(h)) == L.DOP_ERR_INVALID_ARG
+    assert lib().dop_serve_create_mock(ctypes.c_void_p(256), 1 << 20, 2, -1.0,
+                                       ctypes.byref(h)) == L.DOP_ERR_INVALID_ARG

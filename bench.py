@@ -73,6 +73,94 @@ def cpu_baseline(h, p):
     }
 
 
+def _pct(v, q):
+    v = sorted(v)
+    pos = q * (len(v) - 1)
+    i = int(pos)
+    f = pos - i
+    return v[i] * (1 - f) + v[min(i + 1, len(v) - 1)] * f
+
+
+def serve_measure(api, wl, torch, count, rate_hz, pool, slots=4, seed=5):
+    """Replay a Poisson trace of PSF requests twice on the same GPU: through
+    the continuous-batching server (`slots` concurrent requests, arena for
+    `slots` of the largest workspaces) and one request at a time on one
+    stream (the plain path).  Latency = completion - arrival."""
+    import threading
+    trace = wl.serve_trace(count, rate_hz, seed=seed, sizes=tuple(sorted(pool)))
+    reqs = []
+    for r in trace:
+        prob = api.Problem(r["n"], r["m"], r["dx"], r["z"], r["lams"], r["n_index"])
+        reqs.append((r["t"], prob, pool[r["n"]][r["pool"]]))
+    outs = [torch.empty((p.n, p.n), dtype=torch.float32, device="cuda") for _, p, _ in reqs]
+    work = sum(p.k * float(p.m) ** 2 for _, p, _ in reqs) / 1e6
+    torch.cuda.synchronize()
+
+    # one request at a time, in arrival order
+    lat_seq = []
+    t0 = time.perf_counter()
+    for (ta, prob, h), o in zip(reqs, outs):
+        now = time.perf_counter() - t0
+        if now < ta:
+            time.sleep(ta - now)
+        api.psf(h, prob, out=o)
+        torch.cuda.synchronize()
+        lat_seq.append((time.perf_counter() - t0 - ta) * 1e3)
+    span_seq = time.perf_counter() - t0
+
+    # continuous batching
+    big = max(api.workspace_size(p) for _, p, _ in reqs)
+    srv = api.Server(slots * big, max_slots=slots)
+    tickets = [None] * len(reqs)
+    t0 = time.perf_counter()
+
+    def submitter():
+        for i, ((ta, prob, h), o) in enumerate(zip(reqs, outs)):
+            now = time.perf_counter() - t0
+            if now < ta:
+                time.sleep(ta - now)
+            tickets[i] = srv.submit(prob, h, o)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    for t in tickets:
+        srv.wait(t, 600.0)
+    span_srv = time.perf_counter() - t0
+    lat_srv = [srv.latency_ms(t) for t in tickets]
+    peak = srv.stats()["arena_peak"]
+    srv.close()
+    del outs
+    torch.cuda.synchronize()
+    return {
+        "requests": count, "offered_rate_hz": round(rate_hz, 2), "slots": slots,
+        "mpix_lambda": round(work, 1),
+        "served": {"p50_ms": round(_pct(lat_srv, 0.5), 2), "p99_ms": round(_pct(lat_srv, 0.99), 2),
+                   "throughput_req_s": round(count / span_srv, 2),
+                   "mpix_lambda_s": round(work / span_srv, 1), "arena_peak_gb": round(peak / 1e9, 2)},
+        "sequential": {"p50_ms": round(_pct(lat_seq, 0.5), 2),
+                       "p99_ms": round(_pct(lat_seq, 0.99), 2),
+                       "throughput_req_s": round(count / span_seq, 2),
+                       "mpix_lambda_s": round(work / span_seq, 1)},
+    }
+
+
+def design_measure(api, wl, torch, steps=200):
+    """The design workload: 8192^2 heights, 3 wavelengths, padded to 16384^2,
+    L2 loss to a Gaussian target, `steps` Adam steps with cosine decay."""
+    from paper_2505_22313_amd.design import design_loop
+    p = wl.problem("design")
+    n = p["n"]
+    h = torch.from_numpy(wl.heights("design")).cuda()
+    t = torch.from_numpy(wl.gaussian_target(n, 3.0, total=3.0 * n * n)).cuda()
+    prob = api.Problem.from_dict(p)
+    design_loop(h, prob, t, steps=3)  # warm-up
+    _, losses, dt = design_loop(h, prob, t, steps=steps)
+    return {"workload": "8192^2 heights, 3 wavelengths, z=20 mm, padded to 16384^2, "
+                        "Gaussian target sigma=3 px", "steps": steps,
+            "ms_per_step": round(dt * 1e3, 2), "loss_first": losses[0], "loss_last": losses[-1]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +170,9 @@ def main():
     ap.add_argument("--workload", default="large", choices=["large", "mid", "small"])
     ap.add_argument("--lambdas", type=int, default=0,
                     help="profiling runs only: keep the first K wavelengths")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-design", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--calib-copy", action="store_true",
                     help="profiling runs only: first run a plain 4 GiB device copy, the "
                          "reference for HBM byte counters")
@@ -198,6 +289,26 @@ def main():
     if not args.no_cpu_baseline and args.workload == "large":
         log("timing the CPU oracle on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(h, p)
+    del hd, psf
+    ctx.release_workspaces()
+    torch.cuda.empty_cache()
+    if not args.no_design:
+        log("design workload: 200 Adam steps")
+        line["design"] = design_measure(api, wl, torch)
+        ctx.release_workspaces()
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        log("serving: generating the height pool")
+        pool = {n_: [torch.from_numpy(x).cuda() for x in wl.serve_height_pool(n_)]
+                for n_ in (2048, 4096, 8192, 16384)}
+        log("serving: trace at 200 req/s")
+        hot = serve_measure(api, wl, torch, args.serve_requests, 200.0, pool)
+        cap = hot["sequential"]["throughput_req_s"]
+        log(f"serving: trace at 0.7 x capacity ({0.7 * cap:.1f} req/s)")
+        cool = serve_measure(api, wl, torch, args.serve_requests, 0.7 * cap, pool, seed=6)
+        line["serve"] = {"trace": "Poisson arrivals, N in {2048,4096,8192,16384}, M=2N, "
+                                  "1-31 wavelengths over 400-700 nm, z in [5,50] mm",
+                         "at_200_req_s": hot, "at_0.7x_capacity": cool}
     print(json.dumps(line), flush=True)
 
 

@@ -219,3 +219,69 @@ def brute_propagate(u_in, m, dx, lam, z):
             # add this bin's plane wave to the output
             u_out += (coef * hval / (m * m)) * np.outer(np.conj(ky), np.conj(kx))
     return u_out
+
+
+# ---------------------------------------------------------------------------
+# Exact Eq. (3) outputs that can be evaluated one row at a time (for checks at
+# grid sizes whose full M x M field does not fit the oracle's memory).
+# ---------------------------------------------------------------------------
+
+def transfer_value(ky, kx, m, dx, lam, z):
+    """H at individual DFT bins (arrays of integer indices in [0, M)), with the
+    same frequency grid and evanescent test as transfer_function."""
+    f = np.fft.fftfreq(m, d=dx)
+    ay = lam * f[np.asarray(ky)]
+    ax = lam * f[np.asarray(kx)]
+    s = ay * ay + ax * ax
+    prop = s < 1.0
+    root = np.sqrt(np.where(prop, 1.0 - s, 0.0))
+    kz = 2.0 * np.pi * z / lam
+    return np.where(prop, np.exp(1j * (kz * root)), 0.0 + 0.0j)
+
+
+def plane_wave_rows(coeffs, bins, m, dx, lam, z, rows):
+    """Eq. (3) for an unpadded (N = M) input that is a sum of DFT plane waves
+    sum_i c_i exp(2 pi i (u_i y + v_i x) / M): each wave is an eigenfunction,
+    so the output on the given rows is sum_i c_i H(u_i, v_i) (same wave)."""
+    rows = np.asarray(rows)
+    x = np.arange(m)
+    out = np.zeros((len(rows), m), dtype=np.complex128)
+    for c, (u, v) in zip(coeffs, bins):
+        hval = transfer_value([u], [v], m, dx, lam, z)[0]
+        ph = (np.outer((u * rows) % m, np.ones(m, dtype=np.int64)) + (v * x) % m) % m
+        out += c * hval * np.exp(2j * np.pi * ph / m)
+    return out
+
+
+def point_source_rows(n, m, dx, lam, z, src, rows, row_block=256):
+    """Eq. (3) for a unit point source at DOE pixel src = (sy, sx) (centred
+    padding), on the given rows of the N x N output window.
+
+    The padded input is a Kronecker delta, so its spectrum is
+    exp(-2 pi i (u sy' + v sx') / M) with sy' = p0 + sy.  Row y' = p0 + y of
+    the output is the inverse 2-D DFT restricted to that row: the sum over u
+    of exp(2 pi i u y' / M) times the 1-D inverse DFT over v of row u of the
+    filtered spectrum (row-column decomposition, Sec. 4.1), divided by M^2.
+    Returns a complex128 array of shape (len(rows), N).
+    """
+    rows = np.asarray(rows)
+    p0 = pad_offset(n, m)
+    sy, sx = p0 + src[0], p0 + src[1]
+    yo = p0 + rows
+    f = np.fft.fftfreq(m, d=dx)
+    a2 = (lam * f) ** 2
+    kz = 2.0 * np.pi * z / lam
+    v = np.arange(m)
+    phase_x = np.exp(-2j * np.pi * ((v * sx) % m) / m)
+    acc = np.zeros((len(rows), m), dtype=np.complex128)
+    for u0 in range(0, m, row_block):
+        u = np.arange(u0, min(m, u0 + row_block))
+        s = a2[u][:, None] + a2[None, :]
+        prop = s < 1.0
+        hblk = np.where(prop, np.exp(1j * (kz * np.sqrt(np.where(prop, 1.0 - s, 0.0)))), 0.0)
+        spec = hblk * np.exp(-2j * np.pi * ((u * sy) % m) / m)[:, None] * phase_x[None, :]
+        g = sfft.ifft(spec, axis=1, workers=WORKERS) * m        # sum over v, no 1/M yet
+        wy = np.exp(2j * np.pi * ((np.outer(yo, u)) % m) / m)  # (rows, block)
+        acc += wy @ g
+    acc /= float(m) * float(m)
+    return acc[:, p0:p0 + n]

@@ -1,0 +1,65 @@
+"""Differentiable design at the design workload's size (8192^2 heights,
+3 wavelengths, z = 20 mm, padded to 16384^2): the hand-written adjoint
+against the FP64 oracle gradient, and a 200-step Adam run that lowers the
+loss."""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import asm
+from paper_2505_22313_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+asm.WORKERS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_22313_amd import api
+    p = wl.problem("design")
+    h = wl.heights("design")
+    n = p["n"]
+    target = wl.gaussian_target(n, 3.0, total=len(p["lams"]) * float(n) * n)
+    return api, p, h, target
+
+
+@pytest.mark.timeout(900)
+def test_design_gradient_vs_oracle(setup):
+    api, p, h, target = setup
+    n = p["n"]
+    prob = api.Problem.from_dict(p)
+    hd = torch.from_numpy(h).cuda().requires_grad_(True)
+    td = torch.from_numpy(target).cuda()
+    loss = torch.mean((api.DopPSF.apply(hd, prob) - td) ** 2)
+    loss.backward()
+    got = hd.grad.cpu().numpy()
+    torch.cuda.synchronize()
+    print("  oracle forward", flush=True)
+    ps = oracle.psf(h, p["dx"], p["z"], p["m"], p["lams"], p["n_index"])
+    g = 2.0 * (ps - target) / (float(n) * n)
+    print("  oracle gradient", flush=True)
+    want = oracle.psf_backward(h, p["dx"], p["z"], p["m"], p["lams"], p["n_index"], g)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print(f"  gradient rel-L2 {err:.3e}", flush=True)
+    assert err < 1e-4
+    assert abs(loss.item() / np.mean((ps - target) ** 2) - 1) < 1e-5
+
+
+@pytest.mark.timeout(600)
+def test_design_adam_200_steps(setup):
+    api, p, h, target = setup
+    from paper_2505_22313_amd.design import design_loop
+    prob = api.Problem.from_dict(p)
+    hd = torch.from_numpy(h).cuda()
+    td = torch.from_numpy(target).cuda()
+    _, losses, dt = design_loop(hd, prob, td, steps=200, lr=1e-2)
+    print(f"  loss {losses[0]:.4g} -> {losses[-1]:.4g}, {dt * 1e3:.1f} ms/step", flush=True)
+    assert all(np.isfinite(losses))
+    assert losses[-1] < 0.5 * losses[0]

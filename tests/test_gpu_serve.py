@@ -1,0 +1,101 @@
+"""Continuous-batching server on the GPU, through the C ABI.
+
+Each request's PSF must be bitwise identical whether it runs alone (dop_psf
+on one stream) or admitted into the server's mix, where its passes overlap
+with other requests on other streams; a sample is also checked against the
+FP64 oracle.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import asm
+from paper_2505_22313_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+asm.WORKERS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_22313_amd import api as _api
+    return _api
+
+
+def make_requests(api, count, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(count):
+        n = int(rng.choice([256, 384, 512, 1024]))
+        m = 2 * n if n != 384 else 1024
+        k = int(rng.integers(1, 6))
+        lams = np.linspace(0.4, 0.7, k) if k > 1 else np.array([0.55])
+        mode = "full" if rng.random() < 0.25 else "crop"
+        prob = api.Problem(n, m, 1.0, float(rng.uniform(500.0, 5000.0)), lams,
+                           wl.cauchy_index(lams), out_mode=mode)
+        h = torch.from_numpy(wl.uniform_heights(n, seed=1000 * seed + i)).cuda()
+        amp = None
+        if rng.random() < 0.3:
+            amp = torch.from_numpy(wl.circular_aperture(n, 1.0, 0.4 * n)).cuda()
+        reqs.append((prob, h, amp))
+    return reqs
+
+
+def test_serve_bitwise_alone_vs_mix(api):
+    reqs = make_requests(api, 24, seed=7)
+    alone = [api.psf(h, prob, amp=amp).clone() for prob, h, amp in reqs]
+    torch.cuda.synchronize()
+    # arena for about three of the largest workspaces: admission is memory-bound
+    big = max(api.workspace_size(p) for p, _, _ in reqs)
+    srv = api.Server(3 * big, max_slots=4)
+    try:
+        outs = [torch.full(p.out_shape, float("nan"), device="cuda") for p, _, _ in reqs]
+        torch.cuda.synchronize()
+        tickets = [srv.submit(p, h, o, amp=a) for (p, h, a), o in zip(reqs, outs)]
+        for t in tickets:
+            srv.wait(t, 60.0)
+        stats = srv.stats()
+        assert stats["completed"] == len(reqs) and stats["failed"] == 0
+        assert stats["arena_peak"] <= 3 * big
+        for i, (a, b) in enumerate(zip(alone, outs)):
+            assert torch.equal(a, b), f"request {i} differs between alone and mix"
+    finally:
+        srv.close()
+    # a sample against the oracle
+    for i in (0, 5, 11):
+        prob, h, amp = reqs[i]
+        want = oracle.psf(h.cpu().numpy(), prob.dx, prob.z, prob.m, prob.lambdas, prob.n_index,
+                          amp=None if amp is None else amp.cpu().numpy(), out_mode=prob.out_mode)
+        got = alone[i].cpu().numpy()
+        assert np.linalg.norm(got - want) / np.linalg.norm(want) < 2e-5
+
+
+def test_serve_many_small_requests_overlap(api):
+    """Many requests with a roomy arena: all complete, several run at once."""
+    reqs = make_requests(api, 40, seed=11)
+    arena = 8 * max(api.workspace_size(p) for p, _, _ in reqs)
+    srv = api.Server(arena, max_slots=8)
+    try:
+        outs = [torch.empty(p.out_shape, device="cuda") for p, _, _ in reqs]
+        torch.cuda.synchronize()
+        tickets = [srv.submit(p, h, o, amp=a) for (p, h, a), o in zip(reqs, outs)]
+        peak = 0
+        while srv.stats()["completed"] < len(reqs):
+            peak = max(peak, srv.stats()["running"])
+        for t in tickets:
+            srv.wait(t, 60.0)
+        s = srv.stats()
+        assert s["failed"] == 0 and s["completed"] == len(reqs)
+        assert peak >= 2
+        assert s["p50_ms"] <= s["p99_ms"]
+        ref = api.psf(reqs[3][1], reqs[3][0], amp=reqs[3][2])
+        assert torch.equal(ref, outs[3])
+    finally:
+        srv.close()

@@ -264,3 +264,31 @@ def test_adjoint_dot_product():
     lhs = np.vdot(y, px)
     rhs = np.vdot(phy, x)
     assert abs(lhs - rhs) / abs(lhs) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Row-wise exact outputs used at grid sizes the full oracle cannot hold
+# ---------------------------------------------------------------------------
+
+def test_plane_wave_rows_match_propagate():
+    m, dx, lam, z = 64, 0.4, 0.9, 77.0
+    bins = [(0, 3), (5, 60), (31, 31), (17, 2)]      # (31, 31) is evanescent here
+    coeffs = [1.0, 0.5 - 0.2j, 2.0, -0.3j]
+    yy, xx = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
+    field = sum(c * np.exp(2j * np.pi * (u * yy + v * xx) / m) for c, (u, v) in zip(coeffs, bins))
+    full = oracle.propagate(field, m, dx, lam, z, out_mode="full")
+    rows = [0, 7, 63]
+    got = asm.plane_wave_rows(coeffs, bins, m, dx, lam, z, rows)
+    assert rel(got, full[rows]) < 1e-12
+    assert asm.transfer_value([31], [31], m, dx, lam, z)[0] == 0
+
+
+@pytest.mark.parametrize("n,m,src", [(32, 64, (16, 16)), (20, 64, (3, 17)), (64, 64, (0, 63))])
+def test_point_source_rows_match_propagate(n, m, src):
+    dx, lam, z = 0.5, 0.55, 120.0
+    u = np.zeros((n, n), dtype=np.complex128)
+    u[src] = 1.0
+    full = oracle.propagate(u, m, dx, lam, z)
+    rows = [0, src[0], n - 1]
+    got = asm.point_source_rows(n, m, dx, lam, z, src, rows, row_block=16)
+    assert rel(got, full[rows]) < 1e-12

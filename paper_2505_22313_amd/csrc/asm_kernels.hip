@@ -221,13 +221,16 @@ struct LastRegs {
 
 // One Stockham stage S of the L-point DFT along j for every b, followed by the
 // remaining stages.  The first stage reads from SRC (LDS, a load functor
-// ld(j, b), or the register block), every later stage from LDS.  The last
+// ld(j, b), or the register block rin), every later stage from LDS.  The last
 // stage writes natural-order results to SNK (LDS, a store functor
-// st(j, b, v), or the register block).  All threads of the block must call.
+// st(j, b, v), or the register block rout).  hook() runs once, right after
+// the first stage has consumed its inputs (so prefetches issued there do not
+// overlap the first stage's registers).  All threads of the block must call.
 template <class G, bool INV, bool REV, int S, int SRC, int SNK, int THI, class LoadF, class StoreF,
-          int PERR, int RR>
+          class Hook, int PI, int RI, int PO, int RO>
 DEV void stages(float2 *lds, const float2 *twl, const LoadF &ld, const StoreF &st,
-                float2 (&regs)[PERR][RR], const int tid, const int nb_act) {
+                const Hook &hook, float2 (&rin)[PI][RI], float2 (&rout)[PO][RO], const int tid,
+                const int nb_act) {
   constexpr int NSTG = num_stages(G::L);
   constexpr int R = stage_radix(G::L, S, REV);
   constexpr int NS = stage_ns(G::L, S, REV);
@@ -236,7 +239,6 @@ DEV void stages(float2 *lds, const float2 *twl, const LoadF &ld, const StoreF &s
   constexpr int LR = SS::LR, PER = SS::PER, ITEMS = SS::ITEMS;
   static_assert(NS * R <= THI, "twiddle table too small");
   constexpr int TWMUL = THI / (NS * R);  // omega_{NS R}^e = twl[e * TWMUL]
-
   float2 v[PER][R];
   // an item is live if it exists and its batch column is below nb_act (the
   // columns at or beyond nb_act are known to be zero, or are not needed)
@@ -251,9 +253,9 @@ DEV void stages(float2 *lds, const float2 *twl, const LoadF &ld, const StoreF &s
     int j, b;
     if (live(it, j, b)) {
       if constexpr (FIRST && SRC == SRC_REG) {
-        static_assert(PERR == PER && RR == R, "register hand-off shape");
+        static_assert(PI == PER && RI == R, "register input shape");
 #pragma unroll
-        for (int t = 0; t < R; ++t) v[i][t] = regs[i][t];
+        for (int t = 0; t < R; ++t) v[i][t] = rin[i][t];
       } else if constexpr (FIRST && SRC == SRC_FN) {
 #pragma unroll
         for (int t = 0; t < R; ++t) v[i][t] = ld(j + t * LR, b);
@@ -282,6 +284,7 @@ DEV void stages(float2 *lds, const float2 *twl, const LoadF &ld, const StoreF &s
   }
 
   if constexpr (LAST) {
+    if constexpr (FIRST) hook();
     if constexpr (SNK == SNK_LDS) __syncthreads();
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
@@ -291,8 +294,8 @@ DEV void stages(float2 *lds, const float2 *twl, const LoadF &ld, const StoreF &s
 #pragma unroll
         for (int t = 0; t < R; ++t) {
           if constexpr (SNK == SNK_REG) {
-            static_assert(PERR == PER && RR == R, "register hand-off shape");
-            regs[i][t] = v[i][t];
+            static_assert(PO == PER && RO == R, "register output shape");
+            rout[i][t] = v[i][t];
           } else if constexpr (SNK == SNK_FN) {
             st(j + t * LR, b, v[i][t]);
           } else {
@@ -315,18 +318,34 @@ DEV void stages(float2 *lds, const float2 *twl, const LoadF &ld, const StoreF &s
         for (int t = 0; t < R; ++t) lds[(base + t * NS) * G::SJ + b * G::SB] = v[i][t];
       }
     }
+    if constexpr (FIRST) hook();
     __syncthreads();
-    stages<G, INV, REV, S + 1, SRC_LDS, SNK, THI>(lds, twl, ld, st, regs, tid, nb_act);
+    stages<G, INV, REV, S + 1, SRC_LDS, SNK, THI>(lds, twl, ld, st, hook, rin, rout, tid, nb_act);
   }
 }
 
+struct NoHook {
+  DEV void operator()() const {}
+};
+
 // L-point DFT of every batch column of a tile; twl is the LDS table
-// omega_THI^i, i < THI (THI a multiple of L).
+// omega_THI^i, i < THI (THI a multiple of L).  One register block serves as
+// input (SRC_REG) and output (SNK_REG).
 template <class G, bool INV, bool REV, int SRC, int SNK, int THI, class LoadF, class StoreF,
           int PERR, int RR>
 DEV void dft_tile(float2 *lds, const float2 *twl, const LoadF &ld, const StoreF &st,
                   float2 (&regs)[PERR][RR], const int tid, const int nb_act = G::NB) {
-  stages<G, INV, REV, 0, SRC, SNK, THI>(lds, twl, ld, st, regs, tid, nb_act);
+  stages<G, INV, REV, 0, SRC, SNK, THI>(lds, twl, ld, st, NoHook{}, regs, regs, tid, nb_act);
+}
+
+// As dft_tile, with separate input and output register blocks and a hook run
+// after the first stage.
+template <class G, bool INV, bool REV, int SRC, int SNK, int THI, class LoadF, class StoreF,
+          class Hook, int PI, int RI, int PO, int RO>
+DEV void dft_tile_hooked(float2 *lds, const float2 *twl, const LoadF &ld, const StoreF &st,
+                         const Hook &hook, float2 (&rin)[PI][RI], float2 (&rout)[PO][RO],
+                         const int tid, const int nb_act = G::NB) {
+  stages<G, INV, REV, 0, SRC, SNK, THI>(lds, twl, ld, st, hook, rin, rout, tid, nb_act);
 }
 
 // Thread index re-read in every tile iteration through an empty asm
@@ -337,6 +356,15 @@ DEV int loop_tid() {
   asm volatile("" : "+v"(t));
   return t;
 }
+
+// Shape of the first Stockham stage of a tile (what a prefetch must gather).
+template <class G>
+struct FirstStage {
+  static constexpr int R = stage_radix(G::L, 0, false);
+  using SS = StageShape<G, R>;
+  static constexpr int PER = SS::PER, LR = SS::LR, ITEMS = SS::ITEMS;
+  static constexpr bool EXACT = SS::EXACT;
+};
 
 struct NoLoad {
   DEV float2 operator()(int, int) const { return make_float2(0.f, 0.f); }
@@ -477,45 +505,83 @@ DEV float2 transfer(double a2y, double a2x, const KParams &p) {
 // Pass A: DFT over xa for the N input rows, input formed on the fly.
 // Tile = one row y and a run of RA consecutive xb.
 // ---------------------------------------------------------------------------
-template <int LOGM>
+template <int LOGM, int INM>
 DOP_KERNEL(Plan<LOGM>::TA) void k_pass_a_fwd(KParams p) {
   using P = Plan<LOGM>;
-  constexpr int AX = P::AX, BX = P::BX, RA = P::RA, M = P::M, T = P::TA;
+  constexpr int AX = P::AX, BX = P::BX, RA = P::RA, T = P::TA;
   using G = Geo<AX, RA, RA, 1, T, false>;
+  using FS = FirstStage<G>;
   __shared__ float2 lds[AX * RA];
   __shared__ TwLds<LOGM> tw;
   tw_fill<LOGM, T>(tw, p.tw);
   constexpr int RUNS = BX / RA;
   const int ntiles = p.nrows_in * RUNS;
   const int n = p.n;
-  float2 dummy[1][1];
+  // Raw inputs of one tile's first DFT stage, loaded one tile ahead:
+  // (h, amp) for IN_PHASE, the field for IN_FIELD, the saved field for
+  // IN_GRAD; columns x >= n are zero.
+  float2 pre[FS::PER][FS::R];
+  auto fetch = [&](int pt, int tid) {
+    const int tile = xcd_tile(pt, ntiles);
+    const size_t rowin = (size_t)(tile / RUNS) * n;
+    const int xb0 = (tile % RUNS) * RA;
+#pragma unroll
+    for (int i = 0; i < FS::PER; ++i) {
+      const int it = tid + i * T;
+      if (FS::EXACT || it < FS::ITEMS) {
+        int j, b;
+        decode_item<G, FS::R>(it, j, b);
+#pragma unroll
+        for (int t = 0; t < FS::R; ++t) {
+          const int x = BX * (j + t * FS::LR) + xb0 + b;
+          float2 v = make_float2(0.f, 0.f);
+          if (x < n) {
+            const size_t idx = rowin + x;
+            if constexpr (INM == IN_PHASE) v = make_float2(p.h[idx], p.amp ? p.amp[idx] : 1.f);
+            else if constexpr (INM == IN_FIELD) v = p.u_in[idx];
+            else v = p.saved_in[idx];
+          }
+          pre[i][t] = v;
+        }
+      }
+    }
+  };
+  if ((int)blockIdx.x < ntiles) fetch(blockIdx.x, threadIdx.x);
   for (int pt = blockIdx.x; pt < ntiles; pt += gridDim.x) {
     const int tid = loop_tid();
     const int tile = xcd_tile(pt, ntiles);
     const int y = tile / RUNS;
     const int xb0 = (tile % RUNS) * RA;
-    const size_t rowin = (size_t)y * n;
     __syncthreads();
-    auto ld = [&](int xa, int b) -> float2 {
-      const int x = BX * xa + xb0 + b;
-      if (x >= n) return make_float2(0.f, 0.f);
-      const size_t idx = rowin + x;
-      if (p.in_mode == IN_PHASE) {
-        float2 e = doe_phase(p.h[idx], p.phase_turns);
-        if (p.amp) e = cscale(e, p.amp[idx]);
-        return e;
-      } else if (p.in_mode == IN_FIELD) {
-        return p.u_in[idx];
-      } else {
-        return cscale(p.saved_in[idx], p.two_wk * p.gpsf[idx]);
+    // the DOE field (Eq. 1-2) or the caller's field, from the prefetched values
+    float2 v[FS::PER][FS::R];
+#pragma unroll
+    for (int i = 0; i < FS::PER; ++i) {
+      const int it = tid + i * T;
+      if (FS::EXACT || it < FS::ITEMS) {
+        int j, b;
+        decode_item<G, FS::R>(it, j, b);
+#pragma unroll
+        for (int t = 0; t < FS::R; ++t) {
+          const float2 r = pre[i][t];
+          if constexpr (INM == IN_PHASE) {
+            v[i][t] = cscale(doe_phase(r.x, p.phase_turns), r.y);  // r.y = 0 past column n
+          } else if constexpr (INM == IN_FIELD) {
+            v[i][t] = r;
+          } else {
+            const int x = BX * (j + t * FS::LR) + xb0 + b;
+            v[i][t] = x < n ? cscale(r, p.two_wk * p.gpsf[(size_t)y * n + x]) : r;
+          }
+        }
       }
-    };
+    }
+    if (pt + (int)gridDim.x < ntiles) fetch(pt + gridDim.x, tid);
     float2 *out = p.ws + (size_t)y * P::PITCH;
-    auto st = [&](int kxa, int b, float2 v) {
+    auto st = [&](int kxa, int b, float2 w) {
       const int xb = xb0 + b;
-      out[BX * kxa + xb] = cmul(v, tw_q<LOGM>(tw, xb * kxa));
+      out[BX * kxa + xb] = cmul(w, tw_q<LOGM>(tw, xb * kxa));
     };
-    dft_tile<G, false, false, SRC_FN, SNK_FN, P::THI>(lds, tw.hi, ld, st, dummy, tid);
+    dft_tile<G, false, false, SRC_REG, SNK_FN, P::THI>(lds, tw.hi, NoLoad{}, st, v, tid);
   }
 }
 
@@ -533,32 +599,54 @@ DEV void st_pair(float2 *p, float2 a, float2 b) {
 template <int LOGM>
 DOP_KERNEL(Plan<LOGM>::TB) void k_pass_b_fwd(KParams p) {
   using P = Plan<LOGM>;
-  constexpr int AX = P::AX, BX = P::BX, AY = P::AY, BY = P::BY, M = P::M, T = P::TB;
+  constexpr int AX = P::AX, BX = P::BX, AY = P::AY, BY = P::BY, T = P::TB;
   constexpr int SR = BX + 1;  // odd row stride: conflict-free for both DFT directions
   constexpr int HB = BX / 2;  // 16-byte pairs per row segment
+  constexpr int PF = (AY * HB + T - 1) / T;  // pairs each thread moves per tile
   __shared__ float2 lds[AY * SR];
   __shared__ TwLds<LOGM> tw;
   __shared__ float2 rowtw[AY];
   tw_fill<LOGM, T>(tw, p.tw);
   constexpr int NT = AX * BY;
   float2 dummy[1][1];
+  // rows ya with BY*ya + yb >= nrows_in hold zeros: not read, x-DFT skipped
+  auto nzrows = [&](int yb) {
+    return p.nrows_in > yb ? cmin(AY, (p.nrows_in - yb + BY - 1) / BY) : 0;
+  };
+  // Loads of one tile's nonzero rows into registers; issued one tile ahead so
+  // that they are in flight while the current tile is transformed.
+  f4v pre[PF];
+  auto fetch = [&](int pt, int tid) {
+    const int tile = xcd_tile(pt, NT);
+    const int kxa = tile % AX, yb = tile / AX, nz = nzrows(yb);
+    const float2 *src = p.ws + (size_t)yb * P::PITCH + (size_t)BX * kxa;
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int e = tid + i * T, ya = e / HB, c = e % HB;
+      pre[i] = f4v{0.f, 0.f, 0.f, 0.f};
+      if ((PF * T == AY * HB || e < AY * HB) && ya < nz)
+        pre[i] = ld_pair(src + (size_t)(BY * ya) * P::PITCH + 2 * c);
+    }
+  };
+  if (blockIdx.x < NT) fetch(blockIdx.x, threadIdx.x);
   for (int pt = blockIdx.x; pt < NT; pt += gridDim.x) {
     const int tid = loop_tid();
     const int tile = xcd_tile(pt, NT);
     const int kxa = tile % AX;
     const int yb = tile / AX;
     const size_t col0 = (size_t)BX * kxa;
-    // rows ya with BY*ya + yb >= nrows_in hold zeros: not read, x-DFT skipped
-    const int nz = p.nrows_in > yb ? cmin(AY, (p.nrows_in - yb + BY - 1) / BY) : 0;
+    const int nz = nzrows(yb);
     __syncthreads();
     for (int r = tid; r < AY; r += T) rowtw[r] = tw_q<LOGM>(tw, yb * r);  // omega_M^(yb kya)
-    for (int e = tid; e < AY * HB; e += T) {
-      const int ya = e / HB, c = e % HB;
-      f4v v = {0.f, 0.f, 0.f, 0.f};
-      if (ya < nz) v = ld_pair(p.ws + (size_t)(BY * ya + yb) * P::PITCH + col0 + 2 * c);
-      lds[ya * SR + 2 * c] = make_float2(v.x, v.y);
-      lds[ya * SR + 2 * c + 1] = make_float2(v.z, v.w);
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int e = tid + i * T, ya = e / HB, c = e % HB;
+      if (PF * T == AY * HB || e < AY * HB) {
+        lds[ya * SR + 2 * c] = make_float2(pre[i].x, pre[i].y);
+        lds[ya * SR + 2 * c + 1] = make_float2(pre[i].z, pre[i].w);
+      }
     }
+    if (pt + (int)gridDim.x < NT) fetch(pt + gridDim.x, tid);
     __syncthreads();
     using GX = Geo<BX, AY, 1, SR, T, false>;
     dft_tile<GX, false, false, SRC_LDS, SNK_LDS, P::THI>(lds, tw.hi, NoLoad{}, NoStore{}, dummy, tid,
@@ -568,8 +656,8 @@ DOP_KERNEL(Plan<LOGM>::TB) void k_pass_b_fwd(KParams p) {
     for (int e = tid; e < AY * HB; e += T) {
       const int kya = e / HB, c = e % HB;
       const float2 w = rowtw[kya];
-      st_pair(p.ws + (size_t)(BY * kya + yb) * P::PITCH + col0 + 2 * c, cmul(lds[kya * SR + 2 * c], w),
-              cmul(lds[kya * SR + 2 * c + 1], w));
+      st_pair(p.ws + (size_t)(BY * kya + yb) * P::PITCH + col0 + 2 * c,
+              cmul(lds[kya * SR + 2 * c], w), cmul(lds[kya * SR + 2 * c + 1], w));
     }
   }
 }
@@ -634,15 +722,28 @@ DOP_KERNEL(Plan<LOGM>::TC) void k_pass_c(KParams p) {
 template <int LOGM>
 DOP_KERNEL(Plan<LOGM>::TB) void k_pass_b_inv(KParams p) {
   using P = Plan<LOGM>;
-  constexpr int AX = P::AX, BX = P::BX, AY = P::AY, BY = P::BY, M = P::M, T = P::TB;
+  constexpr int AX = P::AX, BX = P::BX, AY = P::AY, BY = P::BY, T = P::TB;
   constexpr int SR = BX + 1;
   constexpr int HB = BX / 2;
+  constexpr int PF = (AY * HB + T - 1) / T;
   __shared__ float2 lds[AY * SR];
   __shared__ TwLds<LOGM> tw;
   __shared__ float2 rowtw[AY];
   tw_fill<LOGM, T>(tw, p.tw);
   constexpr int NT = AX * BY;
   float2 dummy[1][1];
+  f4v pre[PF];
+  auto fetch = [&](int pt, int tid) {
+    const int tile = xcd_tile(pt, NT);
+    const int kxa = tile % AX, yb = tile / AX;
+    const float2 *src = p.ws + (size_t)yb * P::PITCH + (size_t)BX * kxa;
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int e = tid + i * T, kya = e / HB, c = e % HB;
+      if (PF * T == AY * HB || e < AY * HB) pre[i] = ld_pair(src + (size_t)(BY * kya) * P::PITCH + 2 * c);
+    }
+  };
+  if (blockIdx.x < NT) fetch(blockIdx.x, threadIdx.x);
   for (int pt = blockIdx.x; pt < NT; pt += gridDim.x) {
     const int tid = loop_tid();
     const int tile = xcd_tile(pt, NT);
@@ -654,13 +755,16 @@ DOP_KERNEL(Plan<LOGM>::TB) void k_pass_b_inv(KParams p) {
     __syncthreads();
     for (int r = tid; r < AY; r += T) rowtw[r] = tw_q<LOGM>(tw, yb * r);
     __syncthreads();
-    for (int e = tid; e < AY * HB; e += T) {
-      const int kya = e / HB, c = e % HB;
-      const f4v v = ld_pair(p.ws + (size_t)(BY * kya + yb) * P::PITCH + col0 + 2 * c);
-      const float2 w = rowtw[kya];
-      lds[kya * SR + 2 * c] = cmulc(make_float2(v.x, v.y), w);
-      lds[kya * SR + 2 * c + 1] = cmulc(make_float2(v.z, v.w), w);
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int e = tid + i * T, kya = e / HB, c = e % HB;
+      if (PF * T == AY * HB || e < AY * HB) {
+        const float2 w = rowtw[kya];
+        lds[kya * SR + 2 * c] = cmulc(make_float2(pre[i].x, pre[i].y), w);
+        lds[kya * SR + 2 * c + 1] = cmulc(make_float2(pre[i].z, pre[i].w), w);
+      }
     }
+    if (pt + (int)gridDim.x < NT) fetch(pt + gridDim.x, tid);
     __syncthreads();
     using GY = Geo<AY, BX, SR, 1, T, false>;
     dft_tile<GY, true, false, SRC_LDS, SNK_LDS, P::THI>(lds, tw.hi, NoLoad{}, NoStore{}, dummy, tid);
@@ -679,53 +783,115 @@ DOP_KERNEL(Plan<LOGM>::TB) void k_pass_b_inv(KParams p) {
 // Pass A': inverse DFT over kxa for the rows y < nrows_out, then the output
 // stage: PSF accumulation (Eq. 4), field, or height gradient.
 // ---------------------------------------------------------------------------
-template <int LOGM>
+template <int LOGM, int OUTM>
 DOP_KERNEL(Plan<LOGM>::TA) void k_pass_a_inv(KParams p) {
   using P = Plan<LOGM>;
   constexpr int AX = P::AX, BX = P::BX, RA = P::RA, M = P::M, T = P::TA;
   using G = Geo<AX, RA, RA, 1, T, false>;
+  using FS = FirstStage<G>;
+  using LS = LastRegs<G, false>;
+  constexpr int LRL = AX / LS::R;
+  using SSL = StageShape<G, LS::R>;
   __shared__ float2 lds[AX * RA];
   __shared__ TwLds<LOGM> tw;
   tw_fill<LOGM, T>(tw, p.tw);
   constexpr int RUNS = BX / RA;
   const int ntiles = p.nrows_out * RUNS;
   const int n = p.n;
-  float2 dummy[1][1];
+  const bool accumulate = (OUTM == OUT_PSF || OUTM == OUT_GRADH) && !p.first;
+  // spectrum values of one tile's first inverse stage, loaded one tile ahead
+  float2 pre[FS::PER][FS::R];
+  auto fetch = [&](int pt, int tid) {
+    const int tile = xcd_tile(pt, ntiles);
+    const float2 *row = p.ws + (size_t)(tile / RUNS) * P::PITCH + (tile % RUNS) * RA;
+#pragma unroll
+    for (int i = 0; i < FS::PER; ++i) {
+      const int it = tid + i * T;
+      if (FS::EXACT || it < FS::ITEMS) {
+        int j, b;
+        decode_item<G, FS::R>(it, j, b);
+#pragma unroll
+        for (int t = 0; t < FS::R; ++t) pre[i][t] = row[BX * (j + t * FS::LR) + b];
+      }
+    }
+  };
+  // output index of element (xa, b) of the current tile, or -1 if outside
+  auto out_index = [&](int y, int xb0, int xa, int b) -> long long {
+    const int x = BX * xa + xb0 + b;
+    if (p.full) {
+      const int yo = (y + p.p0) & (M - 1), xo = (x + p.p0) & (M - 1);
+      return (long long)yo * M + xo;
+    }
+    return x < n ? (long long)y * n + x : -1;
+  };
+  if ((int)blockIdx.x < ntiles) fetch(blockIdx.x, threadIdx.x);
   for (int pt = blockIdx.x; pt < ntiles; pt += gridDim.x) {
     const int tid = loop_tid();
     const int tile = xcd_tile(pt, ntiles);
     const int y = tile / RUNS;
     const int xb0 = (tile % RUNS) * RA;
-    const float2 *__restrict__ row = p.ws + (size_t)y * P::PITCH;
     __syncthreads();
-    auto ld = [&](int kxa, int b) -> float2 {
-      const int xb = xb0 + b;
-      return cmulc(row[BX * kxa + xb], tw_q<LOGM>(tw, xb * kxa));
-    };
-    auto st = [&](int xa, int b, float2 u) {
-      const int x = BX * xa + xb0 + b;
-      size_t idx;
-      if (p.full) {
-        const int yo = (y + p.p0) & (M - 1), xo = (x + p.p0) & (M - 1);
-        idx = (size_t)yo * M + xo;
-      } else {
-        if (x >= n) return;
-        idx = (size_t)y * n + x;
+    float2 v[FS::PER][FS::R];
+#pragma unroll
+    for (int i = 0; i < FS::PER; ++i) {
+      const int it = tid + i * T;
+      if (FS::EXACT || it < FS::ITEMS) {
+        int j, b;
+        decode_item<G, FS::R>(it, j, b);
+#pragma unroll
+        for (int t = 0; t < FS::R; ++t)
+          v[i][t] = cmulc(pre[i][t], tw_q<LOGM>(tw, (xb0 + b) * (j + t * FS::LR)));
       }
-      if (p.out_mode == OUT_PSF) {
-        const float v = p.wk * (u.x * u.x + u.y * u.y);
-        p.psf[idx] = p.first ? v : p.psf[idx] + v;
-        if (p.saved_out) p.saved_out[idx] = u;
-      } else if (p.out_mode == OUT_FIELD) {
-        p.u_out[idx] = u;
-      } else {
-        float2 e = doe_phase(p.h[idx], p.phase_turns);
-        if (p.amp) e = cscale(e, p.amp[idx]);
-        const float v = p.ck * (u.y * e.x - u.x * e.y);  // c_k Im(g_E conj(E))
-        p.grad_h[idx] = p.first ? v : p.grad_h[idx] + v;
+    }
+    // After the first stage: read the accumulator values this tile will add
+    // to, then start the next tile's loads.  Loads complete in issue order, so
+    // the accumulator reads go first: waiting for them at the end of this
+    // tile must not also wait for the prefetch.
+    float acc[LS::PER][LS::R];
+    auto hook = [&]() {
+#pragma unroll
+      for (int i = 0; i < LS::PER; ++i) {
+        const int it = tid + i * T;
+        int j = 0, b = 0;
+        if (SSL::EXACT || it < SSL::ITEMS) decode_item<G, LS::R>(it, j, b);
+#pragma unroll
+        for (int t = 0; t < LS::R; ++t) {
+          acc[i][t] = 0.f;
+          if (accumulate && (SSL::EXACT || it < SSL::ITEMS)) {
+            const long long idx = out_index(y, xb0, j + t * LRL, b);
+            if (idx >= 0) acc[i][t] = (OUTM == OUT_PSF) ? p.psf[idx] : p.grad_h[idx];
+          }
+        }
       }
+      if (pt + (int)gridDim.x < ntiles) fetch(pt + gridDim.x, tid);
     };
-    dft_tile<G, true, false, SRC_FN, SNK_FN, P::THI>(lds, tw.hi, ld, st, dummy, tid);
+    float2 u[LS::PER][LS::R];
+    dft_tile_hooked<G, true, false, SRC_REG, SNK_REG, P::THI>(lds, tw.hi, NoLoad{}, NoStore{}, hook,
+                                                             v, u, tid);
+#pragma unroll
+    for (int i = 0; i < LS::PER; ++i) {
+      const int it = tid + i * T;
+      if (SSL::EXACT || it < SSL::ITEMS) {
+        int j, b;
+        decode_item<G, LS::R>(it, j, b);
+#pragma unroll
+        for (int t = 0; t < LS::R; ++t) {
+          const long long idx = out_index(y, xb0, j + t * LRL, b);
+          if (idx < 0) continue;
+          const float2 w = u[i][t];
+          if constexpr (OUTM == OUT_PSF) {
+            p.psf[idx] = acc[i][t] + p.wk * (w.x * w.x + w.y * w.y);
+            if (p.saved_out) p.saved_out[idx] = w;
+          } else if constexpr (OUTM == OUT_FIELD) {
+            p.u_out[idx] = w;
+          } else {
+            float2 e = doe_phase(p.h[idx], p.phase_turns);
+            if (p.amp) e = cscale(e, p.amp[idx]);
+            p.grad_h[idx] = acc[i][t] + p.ck * (w.y * e.x - w.x * e.y);  // c_k Im(g_E conj(E))
+          }
+        }
+      }
+    }
   }
 }
 
@@ -747,7 +913,12 @@ static hipError_t launch_impl(const KParams &p, hipStream_t s, hipEvent_t *ev) {
   const unsigned gc = grid((long long)P::AY * (P::M / P::RC));
   const unsigned gai = grid((long long)p.nrows_out * (P::BX / P::RA));
   mark(ev, 0, s);
-  hipLaunchKernelGGL(k_pass_a_fwd<LOGM>, dim3(ga), dim3(P::TA), 0, s, p);
+  if (p.in_mode == IN_PHASE)
+    hipLaunchKernelGGL((k_pass_a_fwd<LOGM, IN_PHASE>), dim3(ga), dim3(P::TA), 0, s, p);
+  else if (p.in_mode == IN_FIELD)
+    hipLaunchKernelGGL((k_pass_a_fwd<LOGM, IN_FIELD>), dim3(ga), dim3(P::TA), 0, s, p);
+  else
+    hipLaunchKernelGGL((k_pass_a_fwd<LOGM, IN_GRAD>), dim3(ga), dim3(P::TA), 0, s, p);
   mark(ev, 1, s);
   hipLaunchKernelGGL(k_pass_b_fwd<LOGM>, dim3(gb), dim3(P::TB), 0, s, p);
   mark(ev, 2, s);
@@ -755,7 +926,12 @@ static hipError_t launch_impl(const KParams &p, hipStream_t s, hipEvent_t *ev) {
   mark(ev, 3, s);
   hipLaunchKernelGGL(k_pass_b_inv<LOGM>, dim3(gb), dim3(P::TB), 0, s, p);
   mark(ev, 4, s);
-  hipLaunchKernelGGL(k_pass_a_inv<LOGM>, dim3(gai), dim3(P::TA), 0, s, p);
+  if (p.out_mode == OUT_PSF)
+    hipLaunchKernelGGL((k_pass_a_inv<LOGM, OUT_PSF>), dim3(gai), dim3(P::TA), 0, s, p);
+  else if (p.out_mode == OUT_FIELD)
+    hipLaunchKernelGGL((k_pass_a_inv<LOGM, OUT_FIELD>), dim3(gai), dim3(P::TA), 0, s, p);
+  else
+    hipLaunchKernelGGL((k_pass_a_inv<LOGM, OUT_GRADH>), dim3(gai), dim3(P::TA), 0, s, p);
   mark(ev, 5, s);
   return hipGetLastError();
 }

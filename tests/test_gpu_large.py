@@ -116,20 +116,30 @@ def test_z0_identity_large(api):
 
 def test_lens_focus_large(api):
     """Ideal lens (f = z = 50 mm, wrapped at 550 nm) over the full 16.4 mm
-    square aperture: sinc^2 focus with peak (L^2/(lambda f))^2."""
+    square aperture.  At this numerical aperture (0.16) the paraxial peak
+    (L^2/(lambda f))^2 is 3.5 % too high; the exact scalar (Rayleigh-Sommerfeld)
+    on-axis amplitude of a converging spherical wave is
+    (f/lambda) * sum over the aperture of dA / (rho^2 + f^2) (Goodman), which
+    the propagated peak must match.  The focal profile keeps the sinc^2 shape
+    of the square pupil."""
     lam = 0.55
     h = torch.from_numpy(wl.fresnel_lens_heights(N, DX, Z)).cuda()
     prob = api.Problem(N, M, DX, Z, [lam], wl.cauchy_index([lam]))
     p = api.psf(h, prob)
     c = N // 2
     side = N * DX
-    i0 = (side * side / (lam * Z)) ** 2
+    coords = (np.arange(N) - c) * DX
+    acc = 0.0
+    for r0 in range(0, N, 2048):
+        y = coords[r0:r0 + 2048][:, None]
+        acc += np.sum(1.0 / (y * y + coords[None, :] ** 2 + Z * Z))
+    i_rs = (Z / lam * acc * DX * DX) ** 2
     win = p[c - 8:c + 9, c - 8:c + 9].double().cpu().numpy()
-    assert abs(win[8, 8] / i0 - 1) < 0.02
+    assert abs(win[8, 8] / i_rs - 1) < 1e-3
     assert np.unravel_index(np.argmax(win), win.shape) == (8, 8)
     x = np.arange(-8, 9) * DX
-    want = i0 * np.sinc(side * x / (lam * Z)) ** 2
-    assert np.max(np.abs(win[8, :] - want)) / i0 < 0.02
-    assert np.max(np.abs(win[:, 8] - want)) / i0 < 0.02
+    shape = np.sinc(side * x / (lam * Z)) ** 2
+    assert np.max(np.abs(win[8, :] / win[8, 8] - shape)) < 0.02
+    assert np.max(np.abs(win[:, 8] / win[8, 8] - shape)) < 0.02
     del h, p
     torch.cuda.empty_cache()

@@ -671,12 +671,33 @@ DOP_KERNEL(Plan<LOGM>::TC) void k_pass_c(KParams p) {
   using P = Plan<LOGM>;
   constexpr int AX = P::AX, BX = P::BX, AY = P::AY, BY = P::BY, M = P::M, RC = P::RC, T = P::TC;
   using G = Geo<BY, RC, RC + 1, 1, T, false>;
+  using FS = FirstStage<G>;
   __shared__ float2 lds[BY * (RC + 1)];
   __shared__ TwLds<LOGM> tw;
   tw_fill<LOGM, T>(tw, p.tw);
   constexpr int RUNS = M / RC;
   constexpr int NT = AY * RUNS;
   using LR_ = LastRegs<G, false>;
+  auto tile_base = [&](int pt) {
+    const int tile = xcd_tile(pt, NT);
+    return p.ws + (size_t)(BY * (tile / RUNS)) * P::PITCH + (tile % RUNS) * RC;
+  };
+  // one tile's first-stage inputs, loaded one tile ahead
+  float2 pre[FS::PER][FS::R];
+  auto fetch = [&](int pt, int tid) {
+    const float2 *base = tile_base(pt);
+#pragma unroll
+    for (int i = 0; i < FS::PER; ++i) {
+      const int it = tid + i * T;
+      if (FS::EXACT || it < FS::ITEMS) {
+        int j, b;
+        decode_item<G, FS::R>(it, j, b);
+#pragma unroll
+        for (int t = 0; t < FS::R; ++t) pre[i][t] = base[(size_t)(j + t * FS::LR) * P::PITCH + b];
+      }
+    }
+  };
+  if ((int)blockIdx.x < NT) fetch(blockIdx.x, threadIdx.x);
   for (int pt = blockIdx.x; pt < NT; pt += gridDim.x) {
     const int tid = loop_tid();
     const int tile = xcd_tile(pt, NT);
@@ -684,11 +705,17 @@ DOP_KERNEL(Plan<LOGM>::TC) void k_pass_c(KParams p) {
     const int kya = tile / RUNS;
     float2 *base = p.ws + (size_t)(BY * kya) * P::PITCH + px0;
     __syncthreads();
-    auto ld = [&](int yb, int b) -> float2 { return base[(size_t)yb * P::PITCH + b]; };
-    auto st = [&](int yb, int b, float2 v) { base[(size_t)yb * P::PITCH + b] = v; };
-
+    float2 v[FS::PER][FS::R];
+#pragma unroll
+    for (int i = 0; i < FS::PER; ++i)
+#pragma unroll
+      for (int t = 0; t < FS::R; ++t) v[i][t] = pre[i][t];
+    auto hook = [&]() {
+      if (pt + (int)gridDim.x < NT) fetch(pt + gridDim.x, tid);
+    };
     float2 regs[LR_::PER][LR_::R];
-    dft_tile<G, false, false, SRC_FN, SNK_REG, P::THI>(lds, tw.hi, ld, NoStore{}, regs, tid);
+    dft_tile_hooked<G, false, false, SRC_REG, SNK_REG, P::THI>(lds, tw.hi, NoLoad{}, NoStore{}, hook,
+                                                              v, regs, tid);
     {
       constexpr int R = LR_::R;
       constexpr int LRn = BY / R;
@@ -711,6 +738,7 @@ DOP_KERNEL(Plan<LOGM>::TC) void k_pass_c(KParams p) {
         }
       }
     }
+    auto st = [&](int yb, int b, float2 w) { base[(size_t)yb * P::PITCH + b] = w; };
     dft_tile<G, true, true, SRC_REG, SNK_FN, P::THI>(lds, tw.hi, NoLoad{}, st, regs, tid);
   }
 }

@@ -445,6 +445,23 @@ DEV int xcd_tile(int p, int ntiles) {
   return (p & ~63) | ((p & 7) << 3) | ((p >> 3) & 7);
 }
 
+// Passes A and A' move runs shorter than a cache line, shared by CH sibling
+// tiles of one row.  A block walks the siblings of a chunk back to back (the
+// chunks themselves in the XCD-aware order), so each line is consumed by one
+// block while it is still in L2 even with the next tile's loads in flight.
+template <int CH>
+struct ChunkSeq {
+  int ntiles, nchunks;
+  DEV explicit ChunkSeq(int n) : ntiles(n), nchunks((n + CH - 1) / CH) {}
+  // k-th tile of this block (k counts the block's own tiles), or -1
+  DEV int tile(int k) const {
+    const int q = (int)blockIdx.x + (k / CH) * (int)gridDim.x;
+    if (q >= nchunks) return -1;
+    const int t = CH * xcd_tile(q, nchunks) + k % CH;
+    return t < ntiles ? t : -2;  // -2: past the end of a short last chunk
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Element-wise physics.
 // ---------------------------------------------------------------------------
@@ -521,8 +538,7 @@ DOP_KERNEL(Plan<LOGM>::TA) void k_pass_a_fwd(KParams p) {
   // (h, amp) for IN_PHASE, the field for IN_FIELD, the saved field for
   // IN_GRAD; columns x >= n are zero.
   float2 pre[FS::PER][FS::R];
-  auto fetch = [&](int pt, int tid) {
-    const int tile = xcd_tile(pt, ntiles);
+  auto fetch = [&](int tile, int tid) {
     const size_t rowin = (size_t)(tile / RUNS) * n;
     const int xb0 = (tile % RUNS) * RA;
 #pragma unroll
@@ -546,10 +562,14 @@ DOP_KERNEL(Plan<LOGM>::TA) void k_pass_a_fwd(KParams p) {
       }
     }
   };
-  if ((int)blockIdx.x < ntiles) fetch(blockIdx.x, threadIdx.x);
-  for (int pt = blockIdx.x; pt < ntiles; pt += gridDim.x) {
+  constexpr int CH = RUNS < 4 ? RUNS : 4;
+  const ChunkSeq<CH> seq(ntiles);
+  if (seq.tile(0) >= 0) fetch(seq.tile(0), threadIdx.x);
+  for (int k = 0;; ++k) {
+    const int tile = seq.tile(k);
+    if (tile == -1) break;
+    if (tile < 0) continue;
     const int tid = loop_tid();
-    const int tile = xcd_tile(pt, ntiles);
     const int y = tile / RUNS;
     const int xb0 = (tile % RUNS) * RA;
     __syncthreads();
@@ -575,7 +595,10 @@ DOP_KERNEL(Plan<LOGM>::TA) void k_pass_a_fwd(KParams p) {
         }
       }
     }
-    if (pt + (int)gridDim.x < ntiles) fetch(pt + gridDim.x, tid);
+    {
+      const int nt = seq.tile(k + 1) >= 0 ? seq.tile(k + 1) : seq.tile(k + 2);
+      if (nt >= 0) fetch(nt, tid);
+    }
     float2 *out = p.ws + (size_t)y * P::PITCH;
     auto st = [&](int kxa, int b, float2 w) {
       const int xb = xb0 + b;
@@ -829,8 +852,7 @@ DOP_KERNEL(Plan<LOGM>::TA) void k_pass_a_inv(KParams p) {
   const bool accumulate = (OUTM == OUT_PSF || OUTM == OUT_GRADH) && !p.first;
   // spectrum values of one tile's first inverse stage, loaded one tile ahead
   float2 pre[FS::PER][FS::R];
-  auto fetch = [&](int pt, int tid) {
-    const int tile = xcd_tile(pt, ntiles);
+  auto fetch = [&](int tile, int tid) {
     const float2 *row = p.ws + (size_t)(tile / RUNS) * P::PITCH + (tile % RUNS) * RA;
 #pragma unroll
     for (int i = 0; i < FS::PER; ++i) {
@@ -852,10 +874,14 @@ DOP_KERNEL(Plan<LOGM>::TA) void k_pass_a_inv(KParams p) {
     }
     return x < n ? (long long)y * n + x : -1;
   };
-  if ((int)blockIdx.x < ntiles) fetch(blockIdx.x, threadIdx.x);
-  for (int pt = blockIdx.x; pt < ntiles; pt += gridDim.x) {
+  constexpr int CH = RUNS < 4 ? RUNS : 4;
+  const ChunkSeq<CH> seq(ntiles);
+  if (seq.tile(0) >= 0) fetch(seq.tile(0), threadIdx.x);
+  for (int k = 0;; ++k) {
+    const int tile = seq.tile(k);
+    if (tile == -1) break;
+    if (tile < 0) continue;
     const int tid = loop_tid();
-    const int tile = xcd_tile(pt, ntiles);
     const int y = tile / RUNS;
     const int xb0 = (tile % RUNS) * RA;
     __syncthreads();
@@ -891,7 +917,8 @@ DOP_KERNEL(Plan<LOGM>::TA) void k_pass_a_inv(KParams p) {
           }
         }
       }
-      if (pt + (int)gridDim.x < ntiles) fetch(pt + gridDim.x, tid);
+      const int nt = seq.tile(k + 1) >= 0 ? seq.tile(k + 1) : seq.tile(k + 2);
+      if (nt >= 0) fetch(nt, tid);
     };
     float2 u[LS::PER][LS::R];
     dft_tile_hooked<G, true, false, SRC_REG, SNK_REG, P::THI>(lds, tw.hi, NoLoad{}, NoStore{}, hook,

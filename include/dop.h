@@ -63,6 +63,16 @@ enum {
   DOP_OUT_FULL = 1   /* the whole M x M plane, in centred coordinates      */
 };
 
+/* Problem flags. */
+enum {
+  /* Band-limited ASM (Matsushima & Shimobaba, Opt. Express 17, 19662,
+   * 2009; one of the ASM variants the paper cites for Eq. (3)): H is also
+   * zero where |fx| >= f_lim or |fy| >= f_lim with
+   * f_lim = 1 / (lambda sqrt((2 |z| / (M dx))^2 + 1)), the frequency beyond
+   * which the sampled transfer function aliases on the M-point grid. */
+  DOP_BANDLIMIT = 1
+};
+
 /* Operation selector for dop_workspace_size. */
 enum { DOP_OP_PROPAGATE = 0, DOP_OP_PSF = 1, DOP_OP_PSF_BACKWARD = 2 };
 
@@ -85,7 +95,7 @@ typedef struct {
   const double *n_index; /* host[K], refractive index n(lambda_k), finite     */
   const float *weight;   /* host[K] PSF weights w_k, or NULL for all 1        */
   int32_t out_mode;      /* DOP_OUT_CROP or DOP_OUT_FULL                      */
-  int32_t flags;         /* must be 0                                         */
+  int32_t flags;         /* 0 or DOP_BANDLIMIT                                */
 } dop_problem;
 
 typedef struct dop_context dop_context;

@@ -15,6 +15,7 @@ Parity status per function (see the module docstrings for the passages):
 """
 
 from .asm import (  # noqa: F401
+    band_limit,
     brute_propagate,
     crop,
     direct_dft2,

@@ -68,37 +68,51 @@ def crop(u, n):
     return u[p0:p0 + n, p0:p0 + n]
 
 
-def transfer_function(m, dx, lam, z):
+def band_limit(m, dx, lam, z):
+    """Matsushima & Shimobaba (2009) band limit of the sampled transfer
+    function: f_lim = 1 / (lam sqrt((2 z / (M dx))^2 + 1)).  Beyond it the
+    phase of H changes by more than pi between neighbouring frequency samples
+    of the M-point grid, so its samples alias."""
+    t = 2.0 * abs(z) / (m * dx)
+    return 1.0 / (lam * np.sqrt(t * t + 1.0))
+
+
+def transfer_function(m, dx, lam, z, bandlimit=False):
     """Angular-spectrum transfer function on the FFT frequency grid (Eq. 3).
 
     Frequencies are numpy's fftfreq (k / (M dx), k signed).  Rows index fy,
     columns index fx.  A frequency propagates iff s < 1 with
     s = (lam*fx)^2 + (lam*fy)^2, each square and the sum rounded once in FP64.
+    With ``bandlimit`` it must also satisfy |fx| < f_lim and |fy| < f_lim
+    (band-limited ASM, one of the propagation variants the paper cites).
     """
     f = np.fft.fftfreq(m, d=dx)
     a = lam * f
     a2 = a * a
     s = a2[:, None] + a2[None, :]
     prop = s < 1.0
+    if bandlimit:
+        inside = np.abs(f) < band_limit(m, dx, lam, z)
+        prop = prop & inside[:, None] & inside[None, :]
     root = np.sqrt(np.where(prop, 1.0 - s, 0.0))
     kz = 2.0 * np.pi * z / lam
     return np.where(prop, np.exp(1j * (kz * root)), 0.0 + 0.0j)
 
 
-def propagate_padded(ep, dx, lam, z, adjoint=False):
+def propagate_padded(ep, dx, lam, z, adjoint=False, bandlimit=False):
     """Eq. (3) on an already padded M x M field: ifft2(fft2(ep) * H).
 
     ``adjoint=True`` applies the adjoint operator ifft2(fft2(ep) * conj(H)).
     """
     m = ep.shape[0]
-    h = transfer_function(m, dx, lam, z)
+    h = transfer_function(m, dx, lam, z, bandlimit=bandlimit)
     if adjoint:
         h = np.conj(h)
     a = sfft.fft2(ep, workers=WORKERS)
     return sfft.ifft2(a * h, workers=WORKERS)
 
 
-def propagate(u_in, m, dx, lam, z, out_mode="crop", adjoint=False):
+def propagate(u_in, m, dx, lam, z, out_mode="crop", adjoint=False, bandlimit=False):
     """Propagate an N x N complex field (zero-padded to M x M) by z.
 
     Returns the N x N crop at [p0, p0+N)^2 (``out_mode="crop"``) or the whole
@@ -106,12 +120,12 @@ def propagate(u_in, m, dx, lam, z, out_mode="crop", adjoint=False):
     """
     u_in = np.asarray(u_in, dtype=np.complex128)
     n = u_in.shape[0]
-    u = propagate_padded(embed(u_in, m), dx, lam, z, adjoint=adjoint)
+    u = propagate_padded(embed(u_in, m), dx, lam, z, adjoint=adjoint, bandlimit=bandlimit)
     return crop(u, n) if out_mode == "crop" else u
 
 
 def psf(h, dx, z, m, lams, n_index, weights=None, amp=None, out_mode="crop",
-        return_fields=False):
+        return_fields=False, bandlimit=False):
     """Eq. (4): sum_k w_k |E_dest,k|^2 over the wavelengths, in k order.
 
     Returns the float64 PSF (N x N crop or M x M full).  With
@@ -128,7 +142,7 @@ def psf(h, dx, z, m, lams, n_index, weights=None, amp=None, out_mode="crop",
     fields = []
     for k in range(k_count):
         e = doe_field(h, lams[k], n_index[k], amp)
-        u = propagate(e, m, dx, lams[k], z, out_mode=out_mode)
+        u = propagate(e, m, dx, lams[k], z, out_mode=out_mode, bandlimit=bandlimit)
         acc += float(weights[k]) * (u.real * u.real + u.imag * u.imag)
         if return_fields:
             fields.append(u)
@@ -136,7 +150,7 @@ def psf(h, dx, z, m, lams, n_index, weights=None, amp=None, out_mode="crop",
 
 
 def psf_backward(h, dx, z, m, lams, n_index, grad_psf, weights=None, amp=None,
-                 out_mode="crop"):
+                 out_mode="crop", bandlimit=False):
     """Gradient dL/dh of a real loss L given G = dL/dPSF (same region as the PSF).
 
     Convention: the gradient of L with respect to a complex field u is
@@ -156,12 +170,12 @@ def psf_backward(h, dx, z, m, lams, n_index, grad_psf, weights=None, amp=None,
     for k in range(k_count):
         e = doe_field(h, lams[k], n_index[k], amp)
         ep = embed(e, m)
-        u = propagate_padded(ep, dx, lams[k], z)
+        u = propagate_padded(ep, dx, lams[k], z, bandlimit=bandlimit)
         if out_mode == "crop":
             g_u = embed(2.0 * float(weights[k]) * g * crop(u, n), m)
         else:
             g_u = 2.0 * float(weights[k]) * g * u
-        g_ep = propagate_padded(g_u, dx, lams[k], z, adjoint=True)
+        g_ep = propagate_padded(g_u, dx, lams[k], z, adjoint=True, bandlimit=bandlimit)
         g_e = crop(g_ep, n)
         c_k = 2.0 * np.pi * (n_index[k] - 1.0) / lams[k]
         grad += c_k * np.imag(g_e * np.conj(e))

@@ -26,6 +26,8 @@ DOP_ERR_NOT_FOUND = -6
 DOP_ERR_SHUTDOWN = -7
 DOP_ERR_TIMEOUT = -8
 
+DOP_BANDLIMIT = 1
+
 DOP_OUT_CROP = 0
 DOP_OUT_FULL = 1
 DOP_OP_PROPAGATE = 0

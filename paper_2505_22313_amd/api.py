@@ -23,7 +23,8 @@ class Problem:
     m x m, pitch dx, distance z, wavelengths, refractive indices n(lambda_k)
     and PSF weights.  Lengths share one unit."""
 
-    def __init__(self, n, m, dx, z, lambdas, n_index, weights=None, out_mode="crop"):
+    def __init__(self, n, m, dx, z, lambdas, n_index, weights=None, out_mode="crop",
+                 bandlimit=False):
         self.n, self.m = int(n), int(m)
         self.dx, self.z = float(dx), float(z)
         self.lambdas = np.ascontiguousarray(np.atleast_1d(lambdas), dtype=np.float64)
@@ -37,6 +38,7 @@ class Problem:
         if out_mode not in OUT_MODES:
             raise ValueError("out_mode must be 'crop' or 'full'")
         self.out_mode = out_mode
+        self.bandlimit = bool(bandlimit)
         self._c = DopProblem()
         c = self._c
         c.n, c.m, c.dx, c.z = self.n, self.m, self.dx, self.z
@@ -46,12 +48,12 @@ class Problem:
         c.weight = (self.weights.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
                     if self.weights is not None else None)
         c.out_mode = OUT_MODES[out_mode]
-        c.flags = 0
+        c.flags = L.DOP_BANDLIMIT if self.bandlimit else 0
 
     @classmethod
-    def from_dict(cls, d, out_mode="crop"):
+    def from_dict(cls, d, out_mode="crop", bandlimit=False):
         return cls(d["n"], d["m"], d["dx"], d["z"], d["lams"], d["n_index"],
-                   d.get("weights"), out_mode=out_mode)
+                   d.get("weights"), out_mode=out_mode, bandlimit=bandlimit)
 
     @property
     def k(self):

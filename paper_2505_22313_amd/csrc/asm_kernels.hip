@@ -493,24 +493,31 @@ DEV double sqrt_unit(double q) {
   return fma(d, h, g);
 }
 
-// (lambda * f)^2 for DFT bin k of M, f = k_signed / (M dx), each product
-// rounded once in FP64 (no contraction), as the evanescent test needs.
-DEV double lam_f_sq(int k, int m, const KParams &p) {
+// Per-axis frequency data of DFT bin k of M: f = k_signed / (M dx), the
+// square (lambda f)^2 with each product rounded once in FP64 (no
+// contraction), as the evanescent test needs, and whether |f| is inside the
+// band limit (always, unless DOP_BANDLIMIT).
+struct AxisFreq {
+  double a2;
+  bool inband;
+};
+DEV AxisFreq axis_freq(int k, int m, const KParams &p) {
 #pragma clang fp contract(off)
   const int ks = k < (m >> 1) ? k : k - m;
   const double f = (double)ks * p.inv_mdx;
   const double a = p.lam * f;
-  return a * a;
+  return AxisFreq{a * a, fabs(f) < p.flim};
 }
 
 // H(ky, kx) / M^2 (conjugated when p.adjoint): zero unless
-// s = a2y + a2x < 1; else exp(i 2 pi (z/lambda) sqrt(1 - s)) with the
-// argument formed and reduced mod one turn in FP64.  Branch-free: evanescent
-// bins evaluate a dummy argument and are scaled by zero.
-DEV float2 transfer(double a2y, double a2x, const KParams &p) {
+// s = a2y + a2x < 1 (and both frequencies inside the band limit); else
+// exp(i 2 pi (z/lambda) sqrt(1 - s)) with the argument formed and reduced mod
+// one turn in FP64.  Branch-free: cut bins evaluate a dummy argument and are
+// scaled by zero.
+DEV float2 transfer(AxisFreq fy, AxisFreq fx, const KParams &p) {
 #pragma clang fp contract(off)
-  const double s = a2y + a2x;
-  const bool prop = s < 1.0;
+  const double s = fy.a2 + fx.a2;
+  const bool prop = s < 1.0 && fy.inband && fx.inband;
   const double t = p.zl * sqrt_unit(prop ? 1.0 - s : 1.0);
   const float2 w = cis_turns((float)(t - rint(t)));
   const float re = prop ? p.inv_m2 : 0.f;
@@ -751,12 +758,12 @@ DOP_KERNEL(Plan<LOGM>::TC) void k_pass_c(KParams p) {
           decode_item<G, R>(it, j, b);
           const int px = px0 + b;
           const int kx = (px / BX) + AX * (px % BX);
-          const double a2x = lam_f_sq(kx, M, p);
+          const AxisFreq fx = axis_freq(kx, M, p);
 #pragma unroll
           for (int t = 0; t < R; ++t) {
             const int kyb = j + t * LRn;
             const int ky = kya + AY * kyb;
-            regs[i][t] = cmul(regs[i][t], transfer(lam_f_sq(ky, M, p), a2x, p));
+            regs[i][t] = cmul(regs[i][t], transfer(axis_freq(ky, M, p), fx, p));
           }
         }
       }

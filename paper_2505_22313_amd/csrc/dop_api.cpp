@@ -75,7 +75,8 @@ dop_status validate_problem(const dop_problem *prob) {
   }
   if (prob->out_mode != DOP_OUT_CROP && prob->out_mode != DOP_OUT_FULL)
     return fail(DOP_ERR_INVALID_ARG, "out_mode must be DOP_OUT_CROP or DOP_OUT_FULL");
-  if (prob->flags != 0) return fail(DOP_ERR_UNSUPPORTED, "flags must be 0");
+  if (prob->flags & ~DOP_BANDLIMIT)
+    return fail(DOP_ERR_UNSUPPORTED, "unknown flags 0x%x", (unsigned)prob->flags);
   // The phase and transfer arguments are reduced in FP64; beyond ~2^40 turns
   // their fractional part would carry no bits.
   for (int k = 0; k < prob->n_lambda; ++k) {
@@ -87,6 +88,15 @@ dop_status validate_problem(const dop_problem *prob) {
 
 size_t workspace_bytes(const dop_problem *prob) {
   return (size_t)prob->m * ((size_t)prob->m + kRowPad) * sizeof(float2);
+}
+
+// Band limit of the sampled transfer function (see DOP_BANDLIMIT), formed
+// exactly as 1 / (lambda sqrt(t t + 1)), t = 2 |z| / (M dx), without FMA
+// contraction, so the mask matches a plain FP64 evaluation bin for bin.
+static double band_limit(double lam, double z, int m, double dx) {
+#pragma clang fp contract(off)
+  const double t = 2.0 * std::fabs(z) / ((double)m * dx);
+  return 1.0 / (lam * std::sqrt(t * t + 1.0));
 }
 
 // Fill the per-wavelength kernel parameters shared by every operation.
@@ -103,6 +113,8 @@ void fill_common(KParams &kp, const dop_context *ctx, const dop_problem *prob, i
   kp.lam = lam;
   kp.zl = prob->z / lam;
   kp.inv_mdx = 1.0 / ((double)prob->m * prob->dx);
+  kp.flim = (prob->flags & DOP_BANDLIMIT) ? band_limit(lam, prob->z, prob->m, prob->dx)
+                                          : HUGE_VAL;
   kp.phase_turns = (prob->n_index[k] - 1.0) / lam;
   const float w = prob->weight ? prob->weight[k] : 1.0f;
   kp.wk = w;

@@ -56,6 +56,7 @@ struct KParams {
   double zl;             // z / lambda_k          (turns at normal incidence)
   double lam;            // lambda_k
   double inv_mdx;        // 1 / (M dx)
+  double flim;           // band limit on |fx| and |fy| (infinity: none)
   float wk;              // PSF weight w_k
   float two_wk;          // 2 w_k
   float ck;              // 2 pi (n_k - 1) / lambda_k

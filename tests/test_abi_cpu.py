@@ -92,8 +92,9 @@ def test_validation_struct_fields():
     p._c.out_mode = 7
     assert _ws(p)[0] == L.DOP_ERR_INVALID_ARG
     p = good()
-    p._c.flags = 1
+    p._c.flags = 2
     assert _ws(p)[0] == L.DOP_ERR_UNSUPPORTED
+    assert _ws(good(bandlimit=True))[0] == L.DOP_OK
     p = good()
     p._c.lambda_ = None
     assert _ws(p)[0] == L.DOP_ERR_INVALID_ARG

@@ -188,3 +188,48 @@ def test_mid_workload_psf(api):
         print(f"  oracle lambda {p['lams'][k]}", flush=True)
         want += oracle.psf(h, p["dx"], p["z"], p["m"], [p["lams"][k]], [p["n_index"][k]])
     assert rel(got, want) < 1e-4
+
+
+# Band-limited ASM: z large against M dx so that f_lim falls well inside the
+# Nyquist band and the cut removes many bins.
+BL_CASES = [
+    (16, 9, 1.0, 0.55, 60.0),
+    (64, 40, 0.5, 0.5, 400.0),
+    (256, 200, 1.0, 0.55, 2000.0),
+    (1024, 700, 0.5, 0.45, -6000.0),
+    (4096, 2048, 1.0, 0.65, 40000.0),
+]
+
+
+@pytest.mark.parametrize("m,n,dx,lam,z", BL_CASES)
+@pytest.mark.parametrize("out_mode", ["crop", "full"])
+def test_propagate_bandlimit_matches_oracle(api, m, n, dx, lam, z, out_mode):
+    flim = asm.band_limit(m, dx, lam, z)
+    assert flim < 0.5 / dx
+    rng = np.random.default_rng(m * 11 + n)
+    u = rand_field(rng, n)
+    prob = api.Problem(n, m, dx, z, [lam], [1.5], out_mode=out_mode, bandlimit=True)
+    got = api.propagate(dev(u, torch.complex64), prob).cpu().numpy()
+    want = oracle.propagate(u.astype(np.complex128), m, dx, lam, z, out_mode=out_mode,
+                            bandlimit=True)
+    assert rel(got, want) < FIELD_TOL
+    plain = oracle.propagate(u.astype(np.complex128), m, dx, lam, z, out_mode=out_mode)
+    assert rel(plain, want) > 1e-3
+
+
+def test_psf_and_backward_bandlimit(api):
+    n, m, dx, z = 256, 512, 1.0, 8000.0
+    lams = np.array([0.45, 0.6])
+    nidx = wl.cauchy_index(lams)
+    w = np.array([1.0, 0.7], dtype=np.float32)
+    rng = np.random.default_rng(46)
+    h = wl.uniform_heights(n, seed=46)
+    g = rng.standard_normal((n, n)).astype(np.float32)
+    prob = api.Problem(n, m, dx, z, lams, nidx, weights=w, bandlimit=True)
+    hd = dev(h, torch.float32)
+    got, saved = api.psf(hd, prob, save_fields=True)
+    want = oracle.psf(h, dx, z, m, lams, nidx, weights=w, bandlimit=True)
+    assert rel(got.cpu().numpy(), want) < INTENSITY_TOL
+    gh = api.psf_backward(hd, prob, saved, dev(g, torch.float32)).cpu().numpy()
+    want_g = oracle.psf_backward(h, dx, z, m, lams, nidx, g, weights=w, bandlimit=True)
+    assert rel(gh, want_g) < GRAD_TOL

@@ -12,6 +12,11 @@ Parity status per function (see the module docstrings for the passages):
   ``propagate``, ``psf``, ``psf_backward``: pinned (brute-force DFT on tiny
   grids, Parseval, z = 0, +-z round trip, plane-wave eigenfunction,
   sinc^2 / Airy lens focus, finite differences, adjoint dot product).
+* ``band_limit`` and the ``bandlimit`` option: pinned (reduces to plain ASM
+  beyond Nyquist, per-bin mask, aliasing removed against a finer grid).
+* ``upsample.upsample``, ``upsample.upsample_adjoint``: pinned (block
+  repetition, closed-form kernel values, interpolation at odd factors,
+  partition of unity, slow cosines, adjoint dot product).
 """
 
 from .asm import (  # noqa: F401
@@ -28,3 +33,4 @@ from .asm import (  # noqa: F401
     psf_backward,
     transfer_function,
 )
+from . import upsample  # noqa: F401

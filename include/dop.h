@@ -73,6 +73,12 @@ enum {
   DOP_BANDLIMIT = 1
 };
 
+/* Interpolation kernels of the super-resolved front end (dop_upsample). */
+enum {
+  DOP_UPSAMPLE_NEAREST = 0,  /* fine sample j takes coarse sample j / s      */
+  DOP_UPSAMPLE_LANCZOS3 = 1  /* separable Lanczos-3, pixel centres aligned  */
+};
+
 /* Operation selector for dop_workspace_size. */
 enum { DOP_OP_PROPAGATE = 0, DOP_OP_PSF = 1, DOP_OP_PSF_BACKWARD = 2 };
 
@@ -80,6 +86,7 @@ enum { DOP_OP_PROPAGATE = 0, DOP_OP_PSF = 1, DOP_OP_PSF_BACKWARD = 2 };
 #define DOP_MAX_M 65536
 #define DOP_MIN_M 16
 #define DOP_MAX_LAMBDA 64
+#define DOP_MAX_UPSAMPLE 16
 
 /*
  * Problem description (paper Sec. 3.1: grid, pitch, wavelengths, index,
@@ -96,6 +103,14 @@ typedef struct {
   const float *weight;   /* host[K] PSF weights w_k, or NULL for all 1        */
   int32_t out_mode;      /* DOP_OUT_CROP or DOP_OUT_FULL                      */
   int32_t flags;         /* 0 or DOP_BANDLIMIT                                */
+  int32_t upsample;      /* 0 or 1: h is the n x n map.  2, 4, 8 or 16 (must
+                            divide n): h is a coarse design of
+                            (n/upsample)^2 samples, nearest-neighbour
+                            upsampled to n x n inside the first pass (paper
+                            Sec. 3.2, Table 2: 8x nearest upsampling).  amp
+                            stays n x n; dop_psf_backward returns the
+                            gradient on the coarse grid.  dop_propagate
+                            requires 0 or 1.                               */
 } dop_problem;
 
 typedef struct dop_context dop_context;
@@ -117,8 +132,10 @@ dop_status dop_context_destroy(dop_context *ctx);
 
 /*
  * Workspace bytes an operation needs for `prob` (op = DOP_OP_*): one M x M
- * c64 field stored with a row pitch of M + 16 elements (8 M (M + 16) bytes).
- * Pure host call.
+ * c64 field stored with a row pitch of M + 16 elements (8 M (M + 16) bytes),
+ * plus, for DOP_OP_PSF_BACKWARD with upsample >= 2, an n x n float32
+ * fine-grid gradient (starting at the next 256-byte boundary).  Pure host
+ * call.
  */
 dop_status dop_workspace_size(const dop_context *ctx, const dop_problem *prob,
                               int op, size_t *bytes);
@@ -134,7 +151,8 @@ dop_status dop_propagate(dop_context *ctx, const dop_problem *prob, int k,
                          size_t ws_bytes, void *stream);
 
 /*
- * Eq. (1)-(4): PSF = sum_k w_k |U_k|^2 for height map `h` (N x N float32)
+ * Eq. (1)-(4): PSF = sum_k w_k |U_k|^2 for height map `h` (N x N float32,
+ * or the coarse (N/upsample)^2 design when prob->upsample >= 2)
  * and optional aperture `amp` (N x N float32, NULL = 1).  `psf` is
  * overwritten: N x N float32 (CROP) or M x M float32 (FULL).  If `saved_u`
  * is not NULL (CROP only) it receives the fields U_k as K x N x N c64, the
@@ -149,14 +167,43 @@ dop_status dop_psf(dop_context *ctx, const dop_problem *prob, const float *h,
  * (N x N float32, CROP only) and the fields saved by dop_psf (K x N x N c64).
  * Per wavelength: g_U = 2 w_k G U_k, g_E = adjoint of Eq. (3) applied to g_U
  * (conj(H_k)), dL/dh += c_k Im(g_E conj(E_k)) with c_k = 2 pi (n_k - 1) /
- * lambda_k and E_k recomputed from h and amp.  `grad_h` (N x N float32) is
- * overwritten.
+ * lambda_k and E_k recomputed from h and amp.  `grad_h` (N x N float32,
+ * or (N/upsample)^2 when prob->upsample >= 2: the fine gradient summed over
+ * each upsample x upsample block) is overwritten.
  */
 dop_status dop_psf_backward(dop_context *ctx, const dop_problem *prob,
                             const float *h, const float *amp,
                             const void *saved_u, const float *grad_psf,
                             float *grad_h, void *ws, size_t ws_bytes,
                             void *stream);
+
+/* ------------------------------------------------------------------------
+ * Super-resolved front end (paper Sec. 3.2 and Table 2: designs on a coarse
+ * feature grid simulated on an s-times finer grid, filled by nearest
+ * neighbour, or by a smooth Lanczos-3 kernel, the interpolation kernels of
+ * its Fig. 4 comparison).  Both maps are separable: fine = W coarse W^T with
+ * a one-axis matrix W of shape (nc s, nc).
+ *   NEAREST:  W[j][i] = 1 iff i = floor(j / s).
+ *   LANCZOS3: fine sample j sits at coarse coordinate u = (j + 0.5)/s - 0.5;
+ *             W[j][i] = L(u - i) for |u - i| < 3 and 0 <= i < nc, with
+ *             L(x) = sinc(x) sinc(x/3), each row divided by its sum
+ *             (weights in FP64, rounded to float32; sums in float32).
+ * Arguments: kind = DOP_UPSAMPLE_*, coarse grid nc x nc (nc >= 1), factor
+ * s in 1..DOP_MAX_UPSAMPLE, nc * s <= DOP_MAX_M.  All arrays are device
+ * float32, row-major, caller-owned and must not overlap.  Asynchronous on
+ * `stream`; arguments are validated before anything is enqueued.
+ * ---------------------------------------------------------------------- */
+
+/* fine ((nc s) x (nc s)) = W coarse (nc x nc) W^T. */
+dop_status dop_upsample(dop_context *ctx, int kind, int nc, int s,
+                        const float *coarse, float *fine, void *stream);
+
+/* grad_coarse (nc x nc) = W^T grad_fine ((nc s) x (nc s)) W: the adjoint,
+ * which carries a fine-grid gradient back to the coarse design (for NEAREST,
+ * the sum over each s x s block). */
+dop_status dop_upsample_adjoint(dop_context *ctx, int kind, int nc, int s,
+                                const float *grad_fine, float *grad_coarse,
+                                void *stream);
 
 /* ------------------------------------------------------------------------
  * Per-pass timing.  While enabled, every wavelength's five passes are

@@ -27,6 +27,9 @@ DOP_ERR_SHUTDOWN = -7
 DOP_ERR_TIMEOUT = -8
 
 DOP_BANDLIMIT = 1
+DOP_UPSAMPLE_NEAREST = 0
+DOP_UPSAMPLE_LANCZOS3 = 1
+DOP_MAX_UPSAMPLE = 16
 
 DOP_OUT_CROP = 0
 DOP_OUT_FULL = 1
@@ -47,6 +50,7 @@ class DopProblem(ctypes.Structure):
         ("weight", ctypes.POINTER(ctypes.c_float)),
         ("out_mode", ctypes.c_int32),
         ("flags", ctypes.c_int32),
+        ("upsample", ctypes.c_int32),
     ]
 
 
@@ -102,6 +106,9 @@ _SIGNATURES = {
     "dop_serve_latency": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]),
     "dop_serve_stats_get": (ctypes.c_int, [_VP, ctypes.POINTER(DopServeStats)]),
     "dop_serve_destroy": (ctypes.c_int, [_VP]),
+    "dop_upsample": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP]),
+    "dop_upsample_adjoint": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP,
+                                            _VP]),
     "dop_profile_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
     "dop_profile_read": (ctypes.c_int, [_VP, ctypes.POINTER(DopPassProfile), ctypes.c_int,
                                         ctypes.POINTER(ctypes.c_int)]),

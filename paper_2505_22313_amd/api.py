@@ -21,10 +21,12 @@ OUT_MODES = {"crop": L.DOP_OUT_CROP, "full": L.DOP_OUT_FULL}
 class Problem:
     """Problem description (paper Sec. 3.1): DOE grid n x n, padded grid
     m x m, pitch dx, distance z, wavelengths, refractive indices n(lambda_k)
-    and PSF weights.  Lengths share one unit."""
+    and PSF weights.  Lengths share one unit.  With upsample = s >= 2 the
+    height map (and its gradient) is the coarse (n/s) x (n/s) design,
+    nearest-neighbour upsampled to n x n inside the first pass."""
 
     def __init__(self, n, m, dx, z, lambdas, n_index, weights=None, out_mode="crop",
-                 bandlimit=False):
+                 bandlimit=False, upsample=1):
         self.n, self.m = int(n), int(m)
         self.dx, self.z = float(dx), float(z)
         self.lambdas = np.ascontiguousarray(np.atleast_1d(lambdas), dtype=np.float64)
@@ -49,6 +51,8 @@ class Problem:
                     if self.weights is not None else None)
         c.out_mode = OUT_MODES[out_mode]
         c.flags = L.DOP_BANDLIMIT if self.bandlimit else 0
+        self.upsample = int(upsample)
+        c.upsample = self.upsample
 
     @classmethod
     def from_dict(cls, d, out_mode="crop", bandlimit=False):
@@ -58,6 +62,12 @@ class Problem:
     @property
     def k(self):
         return len(self.lambdas)
+
+    @property
+    def h_shape(self):
+        """Shape of the height map (the coarse design when upsampled)."""
+        nh = self.n // max(self.upsample, 1)
+        return (nh, nh)
 
     @property
     def out_shape(self):
@@ -183,7 +193,7 @@ def psf(h, prob, amp=None, save_fields=False, ctx=None, out=None):
     With save_fields=True also returns the K x n x n complex64 fields."""
     ctx = ctx or default_context(h.device.index)
     dev = ctx.device
-    _need(h, "h", torch.float32, (prob.n, prob.n), dev)
+    _need(h, "h", torch.float32, prob.h_shape, dev)
     if amp is not None:
         _need(amp, "amp", torch.float32, (prob.n, prob.n), dev)
     if out is None:
@@ -201,17 +211,18 @@ def psf(h, prob, amp=None, save_fields=False, ctx=None, out=None):
 
 
 def psf_backward(h, prob, saved_u, grad_psf, amp=None, ctx=None, out=None):
-    """dL/dh given dL/dPSF (crop) and the fields saved by psf()."""
+    """dL/dh given dL/dPSF (crop) and the fields saved by psf(); dL/dh has
+    the shape of h (the coarse design when upsampled)."""
     ctx = ctx or default_context(h.device.index)
     dev = ctx.device
-    _need(h, "h", torch.float32, (prob.n, prob.n), dev)
+    _need(h, "h", torch.float32, prob.h_shape, dev)
     _need(saved_u, "saved_u", torch.complex64, (prob.k, prob.n, prob.n), dev)
     _need(grad_psf, "grad_psf", torch.float32, (prob.n, prob.n), dev)
     if amp is not None:
         _need(amp, "amp", torch.float32, (prob.n, prob.n), dev)
     if out is None:
-        out = torch.empty((prob.n, prob.n), dtype=torch.float32, device=h.device)
-    _need(out, "out", torch.float32, (prob.n, prob.n), dev)
+        out = torch.empty(prob.h_shape, dtype=torch.float32, device=h.device)
+    _need(out, "out", torch.float32, prob.h_shape, dev)
     stream = _stream_handle(dev)
     nbytes = workspace_size(prob, L.DOP_OP_PSF_BACKWARD)
     ws = ctx.workspace(nbytes, stream)
@@ -244,6 +255,56 @@ def psf_autograd(h, prob, amp=None):
     return DopPSF.apply(h, prob, amp)
 
 
+UPSAMPLE_KINDS = {"nearest": L.DOP_UPSAMPLE_NEAREST, "lanczos3": L.DOP_UPSAMPLE_LANCZOS3}
+
+
+def upsample(coarse, s, kind="nearest", ctx=None, out=None):
+    """Super-resolved front end: the (nc s) x (nc s) map W coarse W^T of an
+    nc x nc float32 design (nearest or Lanczos-3 interpolation)."""
+    ctx = ctx or default_context(coarse.device.index)
+    dev = ctx.device
+    nc = coarse.shape[0]
+    _need(coarse, "coarse", torch.float32, (nc, nc), dev)
+    nf = nc * int(s)
+    if out is None:
+        out = torch.empty((nf, nf), dtype=torch.float32, device=coarse.device)
+    _need(out, "out", torch.float32, (nf, nf), dev)
+    check(lib().dop_upsample(ctx.handle, UPSAMPLE_KINDS[kind], nc, int(s), _ptr(coarse), _ptr(out),
+                             ctypes.c_void_p(_stream_handle(dev))), "dop_upsample")
+    return out
+
+
+def upsample_adjoint(grad_fine, s, kind="nearest", ctx=None, out=None):
+    """W^T grad_fine W: a fine-grid gradient carried back to the design."""
+    ctx = ctx or default_context(grad_fine.device.index)
+    dev = ctx.device
+    nf = grad_fine.shape[0]
+    if nf % int(s):
+        raise ValueError(f"fine size {nf} is not a multiple of {s}")
+    _need(grad_fine, "grad_fine", torch.float32, (nf, nf), dev)
+    nc = nf // int(s)
+    if out is None:
+        out = torch.empty((nc, nc), dtype=torch.float32, device=grad_fine.device)
+    _need(out, "out", torch.float32, (nc, nc), dev)
+    check(lib().dop_upsample_adjoint(ctx.handle, UPSAMPLE_KINDS[kind], nc, int(s),
+                                     _ptr(grad_fine), _ptr(out),
+                                     ctypes.c_void_p(_stream_handle(dev))), "dop_upsample_adjoint")
+    return out
+
+
+class DopUpsample(torch.autograd.Function):
+    """upsample() with upsample_adjoint() as its backward."""
+
+    @staticmethod
+    def forward(fctx, coarse, s, kind="nearest"):
+        fctx.s, fctx.kind = s, kind
+        return upsample(coarse.detach().contiguous(), s, kind)
+
+    @staticmethod
+    def backward(fctx, grad_out):
+        return upsample_adjoint(grad_out.contiguous().to(torch.float32), fctx.s, fctx.kind), None, None
+
+
 class Server:
     """Continuous-batching PSF server over a device arena (see dop.h)."""
 
@@ -274,7 +335,7 @@ class Server:
             hp, ap, op = ctypes.c_void_p(int(h)), None, ctypes.c_void_p(int(out))
         else:
             dev = self.ctx.device
-            _need(h, "h", torch.float32, (prob.n, prob.n), dev)
+            _need(h, "h", torch.float32, prob.h_shape, dev)
             _need(out, "out", torch.float32, prob.out_shape, dev)
             if amp is not None:
                 _need(amp, "amp", torch.float32, (prob.n, prob.n), dev)

@@ -547,6 +547,7 @@ DOP_KERNEL(Plan<LOGM>::TA) void k_pass_a_fwd(KParams p) {
   float2 pre[FS::PER][FS::R];
   auto fetch = [&](int tile, int tid) {
     const size_t rowin = (size_t)(tile / RUNS) * n;
+    const size_t rowh = (size_t)((tile / RUNS) >> p.up_log2) * p.nh;
     const int xb0 = (tile % RUNS) * RA;
 #pragma unroll
     for (int i = 0; i < FS::PER; ++i) {
@@ -560,7 +561,8 @@ DOP_KERNEL(Plan<LOGM>::TA) void k_pass_a_fwd(KParams p) {
           float2 v = make_float2(0.f, 0.f);
           if (x < n) {
             const size_t idx = rowin + x;
-            if constexpr (INM == IN_PHASE) v = make_float2(p.h[idx], p.amp ? p.amp[idx] : 1.f);
+            if constexpr (INM == IN_PHASE)
+              v = make_float2(p.h[rowh + (x >> p.up_log2)], p.amp ? p.amp[idx] : 1.f);
             else if constexpr (INM == IN_FIELD) v = p.u_in[idx];
             else v = p.saved_in[idx];
           }
@@ -947,7 +949,9 @@ DOP_KERNEL(Plan<LOGM>::TA) void k_pass_a_inv(KParams p) {
           } else if constexpr (OUTM == OUT_FIELD) {
             p.u_out[idx] = w;
           } else {
-            float2 e = doe_phase(p.h[idx], p.phase_turns);
+            const int x = BX * (j + t * LRL) + xb0 + b;  // crop only: x < n here
+            float2 e = doe_phase(p.h[(size_t)(y >> p.up_log2) * p.nh + (x >> p.up_log2)],
+                                 p.phase_turns);
             if (p.amp) e = cscale(e, p.amp[idx]);
             p.grad_h[idx] = acc[i][t] + p.ck * (w.y * e.x - w.x * e.y);  // c_k Im(g_E conj(E))
           }

@@ -43,6 +43,9 @@ dop_status fail(dop_status s, const char *fmt, ...) {
 void clear_error() { g_last_error.clear(); }
 
 static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+static int upsample_factor(const dop_problem *prob) {
+  return prob->upsample <= 1 ? 1 : prob->upsample;
+}
 static int ilog2i(int v) {
   int l = 0;
   while ((1 << l) < v) ++l;
@@ -77,6 +80,12 @@ dop_status validate_problem(const dop_problem *prob) {
     return fail(DOP_ERR_INVALID_ARG, "out_mode must be DOP_OUT_CROP or DOP_OUT_FULL");
   if (prob->flags & ~DOP_BANDLIMIT)
     return fail(DOP_ERR_UNSUPPORTED, "unknown flags 0x%x", (unsigned)prob->flags);
+  if (prob->upsample < 0 || prob->upsample > DOP_MAX_UPSAMPLE || !is_pow2(upsample_factor(prob)))
+    return fail(DOP_ERR_UNSUPPORTED, "upsample must be 0, 1, 2, 4, 8 or 16 (got %d)",
+                prob->upsample);
+  if (prob->n % upsample_factor(prob) != 0)
+    return fail(DOP_ERR_INVALID_ARG, "upsample factor %d does not divide n = %d", prob->upsample,
+                prob->n);
   // The phase and transfer arguments are reduced in FP64; beyond ~2^40 turns
   // their fractional part would carry no bits.
   for (int k = 0; k < prob->n_lambda; ++k) {
@@ -88,6 +97,18 @@ dop_status validate_problem(const dop_problem *prob) {
 
 size_t workspace_bytes(const dop_problem *prob) {
   return (size_t)prob->m * ((size_t)prob->m + kRowPad) * sizeof(float2);
+}
+
+// Byte offset of the fine-grid gradient in a DOP_OP_PSF_BACKWARD workspace
+// (present when the design is upsampled): after the field, 256-byte aligned.
+static size_t fine_grad_offset(const dop_problem *prob) {
+  return (workspace_bytes(prob) + 255) & ~(size_t)255;
+}
+
+static size_t workspace_bytes_op(const dop_problem *prob, int op) {
+  if (op == DOP_OP_PSF_BACKWARD && upsample_factor(prob) > 1)
+    return fine_grad_offset(prob) + (size_t)prob->n * prob->n * sizeof(float);
+  return workspace_bytes(prob);
 }
 
 // Band limit of the sampled transfer function (see DOP_BANDLIMIT), formed
@@ -109,6 +130,8 @@ void fill_common(KParams &kp, const dop_context *ctx, const dop_problem *prob, i
   kp.logm = ilog2i(prob->m);
   kp.nrows_in = prob->n;
   kp.p0 = (prob->m - prob->n) / 2;
+  kp.up_log2 = ilog2i(upsample_factor(prob));
+  kp.nh = prob->n >> kp.up_log2;
   const double lam = prob->lambda[k];
   kp.lam = lam;
   kp.zl = prob->z / lam;
@@ -318,15 +341,15 @@ dop_status dop_workspace_size(const dop_context *ctx, const dop_problem *prob, i
     return fail(DOP_ERR_INVALID_ARG, "unknown op %d", op);
   const dop_status s = validate_problem(prob);
   if (s != DOP_OK) return s;
-  *bytes = workspace_bytes(prob);
+  *bytes = workspace_bytes_op(prob, op);
   return DOP_OK;
 }
 
-static dop_status check_ws(const dop_problem *prob, void *ws, size_t ws_bytes) {
+static dop_status check_ws(const dop_problem *prob, int op, void *ws, size_t ws_bytes) {
   if (!ws) return fail(DOP_ERR_WORKSPACE, "workspace is NULL");
-  if (ws_bytes < workspace_bytes(prob))
+  if (ws_bytes < workspace_bytes_op(prob, op))
     return fail(DOP_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes,
-                workspace_bytes(prob));
+                workspace_bytes_op(prob, op));
   if (reinterpret_cast<uintptr_t>(ws) % 16 != 0)
     return fail(DOP_ERR_WORKSPACE, "workspace must be 16-byte aligned");
   return DOP_OK;
@@ -345,7 +368,9 @@ dop_status dop_propagate(dop_context *ctx, const dop_problem *prob, int k, const
   if (!u_in || !u_out) return fail(DOP_ERR_INVALID_ARG, "u_in / u_out must not be NULL");
   if (!aligned(u_in, 8) || !aligned(u_out, 8))
     return fail(DOP_ERR_INVALID_ARG, "complex arrays must be 8-byte aligned");
-  if ((s = check_ws(prob, ws, ws_bytes)) != DOP_OK) return s;
+  if (upsample_factor(prob) != 1)
+    return fail(DOP_ERR_INVALID_ARG, "upsample applies to height maps; dop_propagate needs 0 or 1");
+  if ((s = check_ws(prob, DOP_OP_PROPAGATE, ws, ws_bytes)) != DOP_OK) return s;
   if ((s = check_ctx_device(ctx)) != DOP_OK) return s;
   KParams kp;
   fill_common(kp, ctx, prob, k, ws);
@@ -372,7 +397,7 @@ dop_status dop_psf(dop_context *ctx, const dop_problem *prob, const float *h, co
     return fail(DOP_ERR_UNSUPPORTED, "saved_u requires DOP_OUT_CROP");
   if (saved_u && !aligned(saved_u, 8))
     return fail(DOP_ERR_INVALID_ARG, "saved_u must be 8-byte aligned");
-  if ((s = check_ws(prob, ws, ws_bytes)) != DOP_OK) return s;
+  if ((s = check_ws(prob, DOP_OP_PSF, ws, ws_bytes)) != DOP_OK) return s;
   if ((s = check_ctx_device(ctx)) != DOP_OK) return s;
   return enqueue_psf(ctx, prob, h, amp, psf, saved_u, ws, static_cast<hipStream_t>(stream));
 }
@@ -391,9 +416,14 @@ dop_status dop_psf_backward(dop_context *ctx, const dop_problem *prob, const flo
   if (!aligned(h, 4) || !aligned(grad_psf, 4) || !aligned(grad_h, 4) || !aligned(saved_u, 8) ||
       (amp && !aligned(amp, 4)))
     return fail(DOP_ERR_INVALID_ARG, "misaligned array");
-  if ((s = check_ws(prob, ws, ws_bytes)) != DOP_OK) return s;
+  if ((s = check_ws(prob, DOP_OP_PSF_BACKWARD, ws, ws_bytes)) != DOP_OK) return s;
   if ((s = check_ctx_device(ctx)) != DOP_OK) return s;
   const size_t nn = (size_t)prob->n * prob->n;
+  const int up = upsample_factor(prob);
+  // with an upsampled design the passes accumulate the n x n fine gradient in
+  // the workspace tail; its s x s block sums are the coarse gradient
+  float *grad_fine =
+      up > 1 ? reinterpret_cast<float *>(static_cast<char *>(ws) + fine_grad_offset(prob)) : grad_h;
   for (int k = 0; k < prob->n_lambda; ++k) {
     KParams kp;
     fill_common(kp, ctx, prob, k, ws);
@@ -407,10 +437,58 @@ dop_status dop_psf_backward(dop_context *ctx, const dop_problem *prob, const flo
     kp.amp = amp;
     kp.gpsf = grad_psf;
     kp.saved_in = static_cast<const float2 *>(saved_u) + (size_t)k * nn;
-    kp.grad_h = grad_h;
+    kp.grad_h = grad_fine;
     s = launch(ctx, kp, static_cast<hipStream_t>(stream));
     if (s != DOP_OK) return s;
   }
+  if (up > 1) {
+    const hipError_t e = launch_upsample_adjoint(DOP_UPSAMPLE_NEAREST, prob->n / up, up, grad_fine,
+                                                 grad_h, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+      return fail(DOP_ERR_DEVICE, "upsample adjoint launch failed: %s", hipGetErrorString(e));
+  }
+  return DOP_OK;
+}
+
+static dop_status check_upsample_args(const dop_context *ctx, int kind, int nc, int s,
+                                      const void *in, const void *out) {
+  if (!ctx) return fail(DOP_ERR_INVALID_ARG, "context is NULL");
+  if (kind != DOP_UPSAMPLE_NEAREST && kind != DOP_UPSAMPLE_LANCZOS3)
+    return fail(DOP_ERR_INVALID_ARG, "unknown upsample kind %d", kind);
+  if (nc < 1) return fail(DOP_ERR_INVALID_ARG, "nc must be >= 1 (got %d)", nc);
+  if (s < 1 || s > DOP_MAX_UPSAMPLE)
+    return fail(DOP_ERR_UNSUPPORTED, "factor must be in [1, %d] (got %d)", DOP_MAX_UPSAMPLE, s);
+  if ((long long)nc * s > DOP_MAX_M)
+    return fail(DOP_ERR_UNSUPPORTED, "nc * s = %lld exceeds %d", (long long)nc * s, DOP_MAX_M);
+  if (!in || !out) return fail(DOP_ERR_INVALID_ARG, "arrays must not be NULL");
+  if (!aligned(in, 4) || !aligned(out, 4))
+    return fail(DOP_ERR_INVALID_ARG, "float arrays must be 4-byte aligned");
+  const size_t nf = (size_t)nc * s;
+  const char *a = static_cast<const char *>(in), *b = static_cast<const char *>(out);
+  const size_t na = (size_t)nc * nc * sizeof(float), nb = nf * nf * sizeof(float);
+  if (a < b + nb && b < a + na) return fail(DOP_ERR_INVALID_ARG, "input and output overlap");
+  return check_ctx_device(ctx);
+}
+
+dop_status dop_upsample(dop_context *ctx, int kind, int nc, int s, const float *coarse, float *fine,
+                        void *stream) {
+  clear_error();
+  const dop_status st = check_upsample_args(ctx, kind, nc, s, coarse, fine);
+  if (st != DOP_OK) return st;
+  const hipError_t e = launch_upsample(kind, nc, s, coarse, fine, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(DOP_ERR_DEVICE, "upsample launch failed: %s", hipGetErrorString(e));
+  return DOP_OK;
+}
+
+dop_status dop_upsample_adjoint(dop_context *ctx, int kind, int nc, int s, const float *grad_fine,
+                                float *grad_coarse, void *stream) {
+  clear_error();
+  const dop_status st = check_upsample_args(ctx, kind, nc, s, grad_coarse, grad_fine);
+  if (st != DOP_OK) return st;
+  const hipError_t e = launch_upsample_adjoint(kind, nc, s, grad_fine, grad_coarse,
+                                               static_cast<hipStream_t>(stream));
+  if (e != hipSuccess)
+    return fail(DOP_ERR_DEVICE, "upsample adjoint launch failed: %s", hipGetErrorString(e));
   return DOP_OK;
 }
 

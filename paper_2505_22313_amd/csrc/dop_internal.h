@@ -43,7 +43,10 @@ struct KParams {
   int full;              // 1: output the whole M x M plane (centred)
   int first;             // 1: overwrite the accumulator, 0: add to it
   int adjoint;           // 1: multiply by conj(H)
-  const float *h;        // N x N heights (IN_PHASE, OUT_GRADH)
+  const float *h;        // heights (IN_PHASE, OUT_GRADH): row y, column x of
+                         // the N x N map is h[(y >> up_log2) * nh + (x >> up_log2)]
+  int up_log2;           // log2 of the nearest-neighbour upsampling factor
+  int nh;                // row length of h: N >> up_log2
   const float *amp;      // N x N amplitude or NULL
   const float2 *u_in;    // N x N field (IN_FIELD)
   const float2 *saved_in;// N x N field U_k (IN_GRAD)
@@ -77,6 +80,13 @@ struct PlanInfo {
   int threads_a, threads_b, threads_c;
 };
 bool plan_info(int logm, PlanInfo *out);
+
+// Super-resolved front end: fine = W coarse W^T and its adjoint (kind 0:
+// nearest, 1: Lanczos-3; see dop_upsample).  Arguments already validated.
+hipError_t launch_upsample(int kind, int nc, int s, const float *coarse, float *fine,
+                           hipStream_t stream);
+hipError_t launch_upsample_adjoint(int kind, int nc, int s, const float *grad_fine,
+                                   float *grad_coarse, hipStream_t stream);
 
 }  // namespace dop
 

@@ -74,6 +74,10 @@ def test_workspace_size_valid():
     (dict(lambdas=[-0.5], n_index=[1.5]), L.DOP_ERR_INVALID_ARG),
     (dict(lambdas=[0.5], n_index=[float("nan")]), L.DOP_ERR_INVALID_ARG),
     (dict(z=1e9, lambdas=[1e-4], n_index=[1.5]), L.DOP_ERR_UNSUPPORTED),  # > 1e12 turns
+    (dict(upsample=3), L.DOP_ERR_UNSUPPORTED),       # not a power of two
+    (dict(upsample=32), L.DOP_ERR_UNSUPPORTED),      # beyond 16
+    (dict(upsample=-2), L.DOP_ERR_UNSUPPORTED),
+    (dict(n=500, upsample=8), L.DOP_ERR_INVALID_ARG),  # 8 does not divide 500
 ])
 def test_problem_validation(kw, code):
     st, _ = _ws(good(**kw))
@@ -245,3 +249,51 @@ def test_serve_rejects_bad_create_args():
                                        ctypes.byref(h)) == L.DOP_ERR_INVALID_ARG
     assert lib().dop_serve_create_mock(ctypes.c_void_p(256), 1 << 20, 2, -1.0,
                                        ctypes.byref(h)) == L.DOP_ERR_INVALID_ARG
+
+
+def test_upsampled_problem_workspace():
+    """The backward of an upsampled design needs the fine n x n gradient
+    after the field (256-byte aligned); the other operations do not."""
+    m, n = 1024, 512
+    base = 8 * m * (m + 16)
+    for up in (0, 1):
+        p = good(upsample=up)
+        assert _ws(p, L.DOP_OP_PSF_BACKWARD) == (L.DOP_OK, base)
+    p = good(upsample=8)
+    assert p.h_shape == (64, 64)
+    assert _ws(p, L.DOP_OP_PSF) == (L.DOP_OK, base)
+    assert _ws(p, L.DOP_OP_PSF_BACKWARD) == (L.DOP_OK, ((base + 255) // 256) * 256 + 4 * n * n)
+
+
+def test_propagate_rejects_upsampled_problem():
+    """dop_propagate takes a field, not a height map: upsample must be 0 or
+    1 (checked before the workspace or the context's device are used)."""
+    p = good(upsample=2)
+    st = lib().dop_propagate(ctypes.c_void_p(64), p.ptr(), 0, ctypes.c_void_p(256),
+                             ctypes.c_void_p(4096), None, 0, None)
+    assert st == L.DOP_ERR_INVALID_ARG
+    assert "upsample" in L.last_error()
+
+
+@pytest.mark.parametrize("args,code", [
+    ((0, 64, 8, 256, 1 << 20), L.DOP_ERR_INVALID_ARG),     # NULL context (handled first)
+    ((2, 64, 8, 256, 1 << 20), L.DOP_ERR_INVALID_ARG),     # unknown kind
+    ((1, 0, 8, 256, 1 << 20), L.DOP_ERR_INVALID_ARG),      # nc < 1
+    ((1, 64, 0, 256, 1 << 20), L.DOP_ERR_UNSUPPORTED),     # s < 1
+    ((1, 64, 17, 256, 1 << 20), L.DOP_ERR_UNSUPPORTED),    # s > 16
+    ((0, 8192, 16, 256, 1 << 30), L.DOP_ERR_UNSUPPORTED),  # nc s > 65536
+    ((0, 64, 8, 0, 1 << 20), L.DOP_ERR_INVALID_ARG),       # NULL input
+    ((0, 64, 8, 258, 1 << 20), L.DOP_ERR_INVALID_ARG),     # misaligned
+    ((0, 64, 8, 1 << 20, (1 << 20) + 4096), L.DOP_ERR_INVALID_ARG),  # overlap
+])
+def test_upsample_argument_checks(args, code):
+    """Every argument check runs before the context is dereferenced, so a
+    stand-in handle is safe here (no device is touched)."""
+    kind, nc, s, a, b = args
+    ctx = None if args == (0, 64, 8, 256, 1 << 20) else ctypes.c_void_p(64)
+    st = lib().dop_upsample(ctx, kind, nc, s, ctypes.c_void_p(a) if a else None,
+                            ctypes.c_void_p(b), None)
+    assert st == code, L.last_error()
+    st = lib().dop_upsample_adjoint(ctx, kind, nc, s, ctypes.c_void_p(b),
+                                    ctypes.c_void_p(a) if a else None, None)
+    assert st == code, L.last_error()

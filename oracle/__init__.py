@@ -12,6 +12,8 @@ Parity status per function (see the module docstrings for the passages):
   ``propagate``, ``psf``, ``psf_backward``: pinned (brute-force DFT on tiny
   grids, Parseval, z = 0, +-z round trip, plane-wave eigenfunction,
   sinc^2 / Airy lens focus, finite differences, adjoint dot product).
+* ``psf_lowmem`` (one wavelength, blocked for memory): pinned to ``psf`` at
+  small sizes (same values to rounding), and through it to the pins above.
 * ``band_limit`` and the ``bandlimit`` option: pinned (reduces to plain ASM
   beyond Nyquist, per-bin mask, aliasing removed against a finer grid).
 * ``upsample.upsample``, ``upsample.upsample_adjoint``: pinned (block
@@ -31,6 +33,8 @@ from .asm import (  # noqa: F401
     propagate_padded,
     psf,
     psf_backward,
+    psf_lowmem,
     transfer_function,
+    transfer_rows,
 )
 from . import upsample  # noqa: F401

@@ -30,6 +30,7 @@ ifft2 o diag(conj H) o fft2.
 """
 
 import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import scipy.fft as sfft
@@ -86,14 +87,19 @@ def transfer_function(m, dx, lam, z, bandlimit=False):
     With ``bandlimit`` it must also satisfy |fx| < f_lim and |fy| < f_lim
     (band-limited ASM, one of the propagation variants the paper cites).
     """
+    return transfer_rows(m, dx, lam, z, 0, m, bandlimit=bandlimit)
+
+
+def transfer_rows(m, dx, lam, z, r0, r1, bandlimit=False):
+    """Rows r0 .. r1-1 (fy bins) of ``transfer_function``."""
     f = np.fft.fftfreq(m, d=dx)
     a = lam * f
     a2 = a * a
-    s = a2[:, None] + a2[None, :]
+    s = a2[r0:r1, None] + a2[None, :]
     prop = s < 1.0
     if bandlimit:
         inside = np.abs(f) < band_limit(m, dx, lam, z)
-        prop = prop & inside[:, None] & inside[None, :]
+        prop = prop & inside[r0:r1, None] & inside[None, :]
     root = np.sqrt(np.where(prop, 1.0 - s, 0.0))
     kz = 2.0 * np.pi * z / lam
     return np.where(prop, np.exp(1j * (kz * root)), 0.0 + 0.0j)
@@ -147,6 +153,54 @@ def psf(h, dx, z, m, lams, n_index, weights=None, amp=None, out_mode="crop",
         if return_fields:
             fields.append(u)
     return (acc, fields) if return_fields else acc
+
+
+def psf_lowmem(h, dx, z, m, lam, n_index, block=1024, log=None):
+    """``psf`` for one wavelength (CROP, no amplitude mask, weight 1) on grids
+    whose full-plane temporaries do not fit in memory.
+
+    Same definition, same order of operations per element: the 2-D DFTs are
+    taken as 1-D DFTs along rows and then along columns (the 2-D DFT is
+    separable), each over blocks of rows or columns of one complex128 M x M
+    array, and H is applied one block of rows at a time.  Rows of the padded
+    field outside the DOE are zero, so their row DFTs are skipped; only the
+    N crop rows of the inverse row DFT are taken.  Peak memory is about
+    16 M^2 bytes plus a few blocks.  Returns the N x N float64 PSF.
+    """
+    h = np.asarray(h)
+    n = h.shape[0]
+    p0 = pad_offset(n, m)
+    say = log or (lambda msg: None)
+    ep = np.zeros((m, m), dtype=np.complex128)
+    for r0 in range(0, n, block):
+        r1 = min(n, r0 + block)
+        rows = ep[p0 + r0:p0 + r1]
+        rows[:, p0:p0 + n] = doe_field(h[r0:r1], lam, n_index)
+        ep[p0 + r0:p0 + r1] = sfft.fft(rows, axis=1, workers=WORKERS)
+    say("row DFTs done")
+    for c0 in range(0, m, block):
+        c1 = min(m, c0 + block)
+        ep[:, c0:c1] = sfft.fft(ep[:, c0:c1], axis=0, workers=WORKERS)
+    say("column DFTs done")
+    def apply_h(r0):
+        r1 = min(m, r0 + hblock)
+        ep[r0:r1] *= transfer_rows(m, dx, lam, z, r0, r1)
+
+    hblock = max(1, min(block, (1 << 24) // m))  # about 1 GB of temporaries per thread
+    with ThreadPoolExecutor(WORKERS) as pool:
+        list(pool.map(apply_h, range(0, m, hblock)))
+    say("transfer function applied")
+    for c0 in range(0, m, block):
+        c1 = min(m, c0 + block)
+        ep[:, c0:c1] = sfft.ifft(ep[:, c0:c1], axis=0, workers=WORKERS)
+    say("inverse column DFTs done")
+    out = np.empty((n, n), dtype=np.float64)
+    for r0 in range(0, n, block):
+        r1 = min(n, r0 + block)
+        u = sfft.ifft(ep[p0 + r0:p0 + r1], axis=1, workers=WORKERS)[:, p0:p0 + n]
+        out[r0:r1] = u.real * u.real + u.imag * u.imag
+    say("inverse row DFTs done")
+    return out
 
 
 def psf_backward(h, dx, z, m, lams, n_index, grad_psf, weights=None, amp=None,

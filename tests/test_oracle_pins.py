@@ -409,3 +409,13 @@ def test_upsample_adjoint_dot_product(kind, s):
     lhs = np.sum(ups.upsample(x, s, kind) * g)
     rhs = np.sum(x * ups.upsample_adjoint(g, s, kind))
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs) + 1e-12
+
+
+@pytest.mark.parametrize("n,m,block", [(48, 128, 16), (100, 256, 64), (64, 64, 1000)])
+def test_psf_lowmem_equals_psf(n, m, block):
+    """The memory-lean single-wavelength PSF (1-D DFTs over blocks of rows and
+    columns) is the same definition: it matches psf() to rounding."""
+    h = np.random.default_rng(n).uniform(0, 1.2, (n, n))
+    a = oracle.psf(h, 0.5, 300.0, m, [0.55], [1.46])
+    b = oracle.psf_lowmem(h, 0.5, 300.0, m, 0.55, 1.46, block=block)
+    assert rel(b, a) < 1e-12

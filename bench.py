@@ -177,6 +177,71 @@ def design_measure(api, wl, torch, steps=200):
             "ms_per_step": round(dt * 1e3, 2), "loss_first": losses[0], "loss_last": losses[-1]}
 
 
+def _event_ms(torch, fn, reps):
+    """Average ms of fn() over reps runs, timed with HIP events on the current stream."""
+    fn()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def copy_ceiling_gbs(torch, nbytes=1 << 32):
+    """Device-to-device copy rate (read + write bytes per second), the
+    practical ceiling of a read+write pass on this GPU."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    ms = _event_ms(torch, lambda: dst.copy_(src), 5)
+    del src, dst
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def variants_measure(api, wl, torch, p, hd, ctx, base_ms):
+    """The NEXT-row options on the same workload: nearest 8x upsampling fused
+    into pass A (a 4096^2 design on the 32768^2 grid), band-limited ASM, and
+    the standalone Lanczos-3 upsampling kernel and its adjoint."""
+    n, k = p["n"], len(p["lams"])
+    s = 8
+    hc = hd[::s, ::s].contiguous()
+    out = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    res = {}
+    pu = api.Problem(n, p["m"], p["dx"], p["z"], p["lams"], p["n_index"], p.get("weights"),
+                     upsample=s)
+    ctx.profile_enable(True)
+    ms = _event_ms(torch, lambda: api.psf(hc, pu, out=out, ctx=ctx), 1)
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    res["upsample_nearest_fused"] = {
+        "factor": s, "design": f"{n // s}^2 -> {n}^2", "ms_per_step": round(ms, 2),
+        "vs_plain_step": round(ms / base_ms, 4),
+        "pass_a_fwd_avg_ms": round(prof["pass_a_fwd"][1] / max(prof["pass_a_fwd"][0], 1), 4)}
+    pb = api.Problem(n, p["m"], p["dx"], p["z"], p["lams"], p["n_index"], p.get("weights"),
+                     bandlimit=True)
+    ctx.profile_enable(True)
+    ms = _event_ms(torch, lambda: api.psf(hd, pb, out=out, ctx=ctx), 1)
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    res["bandlimit"] = {"ms_per_step": round(ms, 2), "vs_plain_step": round(ms / base_ms, 4),
+                        "pass_c_avg_ms": round(prof["pass_c"][1] / max(prof["pass_c"][0], 1), 4)}
+    del out
+    fine = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    ms_up = _event_ms(torch, lambda: api.upsample(hc, s, "lanczos3", ctx=ctx, out=fine), 3)
+    gc = torch.empty_like(hc)
+    ms_adj = _event_ms(torch, lambda: api.upsample_adjoint(fine, s, "lanczos3", ctx=ctx, out=gc), 3)
+    nbytes = 4.0 * (n * n + (n // s) ** 2)
+    res["lanczos3_kernels"] = {
+        "factor": s, "design": f"{n // s}^2 -> {n}^2",
+        "upsample_ms": round(ms_up, 3), "upsample_alg_gbs": round(nbytes / (ms_up * 1e-3) / 1e9, 1),
+        "adjoint_ms": round(ms_adj, 3), "adjoint_alg_gbs": round(nbytes / (ms_adj * 1e-3) / 1e9, 1),
+        "share_of_step": round((ms_up + ms_adj) / base_ms, 5), "n_lambda": k}
+    del fine, gc, hc
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +254,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-design", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the upsampling / band-limit measurements")
     ap.add_argument("--calib-copy", action="store_true",
                     help="profiling runs only: first run a plain 4 GiB device copy, the "
                          "reference for HBM byte counters")
@@ -265,6 +332,8 @@ def main():
     step_bytes = sum(first.values()) + (k - 1) * sum(per_lambda.values())
     torch.cuda.synchronize()
     sumv = float(psf.double().sum().item())
+    copy_gbs = copy_ceiling_gbs(torch)
+    log(f"device copy ceiling {copy_gbs:.0f} GB/s")
 
     line = {
         "metric": METRIC,
@@ -289,6 +358,7 @@ def main():
             }[args.workload],
             "n": n, "m": m, "n_lambda": k, "dx_um": p["dx"], "z_um": p["z"],
         },
+        "value_unpadded": round(k * float(n) * n / dt / 1e6, 1),
         "hbm_gbs_alg": round(step_bytes / dt / 1e9, 1),
         "alg_bytes_per_padded_pixel_lambda": round(step_bytes / (k * float(m) * m), 2),
         "passes": {kk: {"avg_ms": v["avg_ms"], "alg_gbs": v["alg_gbs"]} for kk, v in passes.items()},
@@ -300,9 +370,14 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            "copy_ceiling_gbs": round(copy_gbs, 1),
+            "frac_of_copy": round(achieved / copy_gbs, 4),
         },
         "psf_sum": sumv,
     }
+    if not args.no_variants and args.workload == "large" and not args.lambdas:
+        log("variants: fused 8x nearest upsampling, band limit, Lanczos-3 kernels")
+        line["variants"] = variants_measure(api, wl, torch, p, hd, ctx, dt * 1e3)
     if not args.no_cpu_baseline and args.workload == "large":
         log("timing the CPU oracle on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(h, p)

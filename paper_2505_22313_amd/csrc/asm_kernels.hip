@@ -374,8 +374,10 @@ struct NoStore {
 };
 
 // ---------------------------------------------------------------------------
-// Pass plan per log2(M).  Tiles hold at most 8192 points (64 KiB + padding),
-// so two blocks fit in one CU's 160 KiB LDS.
+// Pass plan per log2(M).  Tiles of passes B and C hold at most 8192 points
+// (64 KiB + padding), so two blocks fit in one CU's 160 KiB LDS; tiles of
+// passes A and A' hold up to 16384 (one block per CU) so that every row run
+// they move is a whole 128-byte line.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 __host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
@@ -396,9 +398,11 @@ struct Plan {
   static constexpr int AX = M / BX;
   static constexpr int AY = 1 << plan_ay(LOGM);
   static constexpr int BY = M / AY;
-  static constexpr int RA = cmin(8, BX);   // contiguous run in passes A / A'
+  static constexpr int RA = cmin(16, BX);  // contiguous run in passes A / A': a 128-byte line
   static constexpr int RC = cmin(16, M);   // contiguous run in pass C
-  static constexpr int TA = threads_for(AX * RA);
+  // A / A' tiles (up to 1024 x 16 points, 128 KiB of LDS) run one block of
+  // up to 1024 threads per CU
+  static constexpr int TA = cmin(1024, cmax(64, AX * RA / 16));
   static constexpr int TB = threads_for(BX * AY);
   static constexpr int TC = threads_for(BY * RC);
   // Twiddles in LDS: omega_M^q = HI[q / S] * LO[q % S] with HI[i] = omega_M^(i S)
@@ -445,8 +449,8 @@ DEV int xcd_tile(int p, int ntiles) {
   return (p & ~63) | ((p & 7) << 3) | ((p >> 3) & 7);
 }
 
-// Passes A and A' move runs shorter than a cache line, shared by CH sibling
-// tiles of one row.  A block walks the siblings of a chunk back to back (the
+// Passes A and A' read heights and read-modify-write the PSF in float runs
+// shorter than a cache line, shared by CH sibling tiles of one row.  A block walks the siblings of a chunk back to back (the
 // chunks themselves in the XCD-aware order), so each line is consumed by one
 // block while it is still in L2 even with the next tile's loads in flight.
 template <int CH>
@@ -480,17 +484,15 @@ DEV float2 doe_phase(float hv, double turns_per_h) {
   return cis_turns((float)(q - rint(q)));
 }
 
-// sqrt(q) for q in (0, 1] in FP64: FP32 reciprocal-square-root seed, one
-// Goldschmidt iteration (relative error ~1e-14), then a Newton correction of
-// the root (about 1 ulp).
+// sqrt(q) for q in (0, 1] in FP64: FP32 reciprocal-square-root seed (relative
+// error below 2^-22) and one Goldschmidt iteration, which squares the error:
+// below 3e-14 relative.  Times z/lambda <= 2^17 turns that is under 4e-9 turn
+// of phase, far below the 1.3e-7 turn error of the FP32 sin/cos that follows.
 DEV double sqrt_unit(double q) {
   const double r = (double)__builtin_amdgcn_rsqf((float)q);
-  double g = q * r, h = 0.5 * r;
+  const double g = q * r, h = 0.5 * r;
   const double e = fma(-g, h, 0.5);
-  g = fma(g, e, g);
-  h = fma(h, e, h);
-  const double d = fma(-g, g, q);
-  return fma(d, h, g);
+  return fma(g, e, g);
 }
 
 // Per-axis frequency data of DFT bin k of M: f = k_signed / (M dx), the
@@ -509,15 +511,19 @@ DEV AxisFreq axis_freq(int k, int m, const KParams &p) {
   return AxisFreq{a * a, fabs(f) < p.flim};
 }
 
-// H(ky, kx) / M^2 (conjugated when p.adjoint): zero unless
-// s = a2y + a2x < 1 (and both frequencies inside the band limit); else
-// exp(i 2 pi (z/lambda) sqrt(1 - s)) with the argument formed and reduced mod
-// one turn in FP64.  Branch-free: cut bins evaluate a dummy argument and are
-// scaled by zero.
-DEV float2 transfer(AxisFreq fy, AxisFreq fx, const KParams &p) {
+// (lambda f)^2 of one axis with the band limit folded in: a frequency outside
+// the band gets 2, so that s >= 1 below whatever the other axis holds (an
+// in-band s is unchanged).
+DEV double a2_eff(AxisFreq f) { return f.inband ? f.a2 : 2.0; }
+
+// H(ky, kx) / M^2 (conjugated when p.adjoint) from the two axes' a2_eff: zero
+// unless s = a2y + a2x < 1; else exp(i 2 pi (z/lambda) sqrt(1 - s)) with the
+// argument formed and reduced mod one turn in FP64.  Branch-free: cut bins
+// evaluate a dummy argument and are scaled by zero.
+DEV float2 transfer(double a2y, double a2x, const KParams &p) {
 #pragma clang fp contract(off)
-  const double s = fy.a2 + fx.a2;
-  const bool prop = s < 1.0 && fy.inband && fx.inband;
+  const double s = a2y + a2x;
+  const bool prop = s < 1.0;
   const double t = p.zl * sqrt_unit(prop ? 1.0 - s : 1.0);
   const float2 w = cis_turns((float)(t - rint(t)));
   const float re = prop ? p.inv_m2 : 0.f;
@@ -704,9 +710,13 @@ DOP_KERNEL(Plan<LOGM>::TC) void k_pass_c(KParams p) {
   constexpr int AX = P::AX, BX = P::BX, AY = P::AY, BY = P::BY, M = P::M, RC = P::RC, T = P::TC;
   using G = Geo<BY, RC, RC + 1, 1, T, false>;
   using FS = FirstStage<G>;
+  static_assert((size_t)BY * P::PITCH < (1ull << 31), "tile offsets are 32-bit");
   __shared__ float2 lds[BY * (RC + 1)];
-  __shared__ TwLds<LOGM> tw;
-  tw_fill<LOGM, T>(tw, p.tw);
+  // only BY-point DFTs run here: their twiddles omega_BY^i, i < BY
+  __shared__ float2 twc[BY];
+  // a2_eff of the tile's BY frequency rows
+  __shared__ double a2row[BY];
+  for (int i = threadIdx.x; i < BY; i += T) twc[i] = p.tw[i << (kTwLog - ilog2c(BY))];
   constexpr int RUNS = M / RC;
   constexpr int NT = AY * RUNS;
   using LR_ = LastRegs<G, false>;
@@ -725,7 +735,8 @@ DOP_KERNEL(Plan<LOGM>::TC) void k_pass_c(KParams p) {
         int j, b;
         decode_item<G, FS::R>(it, j, b);
 #pragma unroll
-        for (int t = 0; t < FS::R; ++t) pre[i][t] = base[(size_t)(j + t * FS::LR) * P::PITCH + b];
+        for (int t = 0; t < FS::R; ++t)
+          pre[i][t] = base[(unsigned)(j + t * FS::LR) * (unsigned)P::PITCH + (unsigned)b];
       }
     }
   };
@@ -737,6 +748,9 @@ DOP_KERNEL(Plan<LOGM>::TC) void k_pass_c(KParams p) {
     const int kya = tile / RUNS;
     float2 *base = p.ws + (size_t)(BY * kya) * P::PITCH + px0;
     __syncthreads();
+    // frequency rows of this tile: position kyb holds ky = kya + AY kyb; read
+    // after the forward DFT, whose stage barriers order this write before them
+    for (int r = tid; r < BY; r += T) a2row[r] = a2_eff(axis_freq(kya + AY * r, M, p));
     float2 v[FS::PER][FS::R];
 #pragma unroll
     for (int i = 0; i < FS::PER; ++i)
@@ -746,8 +760,8 @@ DOP_KERNEL(Plan<LOGM>::TC) void k_pass_c(KParams p) {
       if (pt + (int)gridDim.x < NT) fetch(pt + gridDim.x, tid);
     };
     float2 regs[LR_::PER][LR_::R];
-    dft_tile_hooked<G, false, false, SRC_REG, SNK_REG, P::THI>(lds, tw.hi, NoLoad{}, NoStore{}, hook,
-                                                              v, regs, tid);
+    dft_tile_hooked<G, false, false, SRC_REG, SNK_REG, BY>(lds, twc, NoLoad{}, NoStore{}, hook, v,
+                                                          regs, tid);
     {
       constexpr int R = LR_::R;
       constexpr int LRn = BY / R;
@@ -760,18 +774,17 @@ DOP_KERNEL(Plan<LOGM>::TC) void k_pass_c(KParams p) {
           decode_item<G, R>(it, j, b);
           const int px = px0 + b;
           const int kx = (px / BX) + AX * (px % BX);
-          const AxisFreq fx = axis_freq(kx, M, p);
+          const double a2x = a2_eff(axis_freq(kx, M, p));
 #pragma unroll
-          for (int t = 0; t < R; ++t) {
-            const int kyb = j + t * LRn;
-            const int ky = kya + AY * kyb;
-            regs[i][t] = cmul(regs[i][t], transfer(axis_freq(ky, M, p), fx, p));
-          }
+          for (int t = 0; t < R; ++t)
+            regs[i][t] = cmul(regs[i][t], transfer(a2row[j + t * LRn], a2x, p));
         }
       }
     }
-    auto st = [&](int yb, int b, float2 w) { base[(size_t)yb * P::PITCH + b] = w; };
-    dft_tile<G, true, true, SRC_REG, SNK_FN, P::THI>(lds, tw.hi, NoLoad{}, st, regs, tid);
+    auto st = [&](int yb, int b, float2 w) {
+      base[(unsigned)yb * (unsigned)P::PITCH + (unsigned)b] = w;
+    };
+    dft_tile<G, true, true, SRC_REG, SNK_FN, BY>(lds, twc, NoLoad{}, st, regs, tid);
   }
 }
 

@@ -531,6 +531,18 @@ DEV float2 transfer(double a2y, double a2x, const KParams &p) {
   return make_float2(w.x * re, w.y * im);
 }
 
+// Element at a 32-bit byte offset from a block-uniform base: the offset is
+// formed in 32-bit arithmetic so the access can take a scalar base plus one
+// 32-bit vector offset instead of a 64-bit address per lane.
+template <class T>
+DEV T *at_byte(T *base, unsigned off) {
+  return reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off);
+}
+template <class T>
+DEV const T *at_byte(const T *base, unsigned off) {
+  return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
+}
+
 // ---------------------------------------------------------------------------
 // Pass A: DFT over xa for the N input rows, input formed on the fly.
 // Tile = one row y and a run of RA consecutive xb.
@@ -736,7 +748,7 @@ DOP_KERNEL(Plan<LOGM>::TC) void k_pass_c(KParams p) {
         decode_item<G, FS::R>(it, j, b);
 #pragma unroll
         for (int t = 0; t < FS::R; ++t)
-          pre[i][t] = base[(unsigned)(j + t * FS::LR) * (unsigned)P::PITCH + (unsigned)b];
+          pre[i][t] = *at_byte(base, ((unsigned)(j + t * FS::LR) * (unsigned)P::PITCH + b) * 8u);
       }
     }
   };
@@ -782,7 +794,7 @@ DOP_KERNEL(Plan<LOGM>::TC) void k_pass_c(KParams p) {
       }
     }
     auto st = [&](int yb, int b, float2 w) {
-      base[(unsigned)yb * (unsigned)P::PITCH + (unsigned)b] = w;
+      *at_byte(base, ((unsigned)yb * (unsigned)P::PITCH + b) * 8u) = w;
     };
     dft_tile<G, true, true, SRC_REG, SNK_FN, BY>(lds, twc, NoLoad{}, st, regs, tid);
   }

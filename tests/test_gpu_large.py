@@ -143,3 +143,23 @@ def test_lens_focus_large(api):
     assert np.max(np.abs(win[:, 8] / win[8, 8] - shape)) < 0.02
     del h, p
     torch.cuda.empty_cache()
+
+
+LARGE_PSF = os.path.join(os.path.dirname(__file__), "golden", "psf_large_550nm_rows.npz")
+
+
+def test_large_workload_psf_rows_vs_oracle(api):
+    """The large workload itself (seeded 32768^2 lens + noise heights, 65536^2
+    grid) at 550 nm: 12 whole rows of the PSF against the FP64 oracle
+    (tests/golden/make_large_psf_golden.py), plus the crop's total and peak."""
+    g = np.load(LARGE_PSF)
+    assert (int(g["n"]), int(g["m"]), float(g["dx"]), float(g["z"])) == (N, M, DX, Z)
+    h = torch.from_numpy(wl.heights("large")).cuda()
+    prob = api.Problem(N, M, DX, Z, [float(g["lam"])], [float(g["n_index"])])
+    out = api.psf(h, prob)
+    got = out[torch.from_numpy(g["rows"]).cuda()].double().cpu().numpy()
+    assert rel(got, g["psf_rows"].astype(np.float64)) < 1e-4
+    assert abs(float(out.sum(dtype=torch.float64).item()) / float(g["total"]) - 1) < 1e-5
+    assert abs(float(out.max().item()) / float(g["peak"]) - 1) < 1e-4
+    del h, out
+    torch.cuda.empty_cache()

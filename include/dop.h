@@ -47,8 +47,8 @@ typedef enum {
   DOP_OK = 0,
   DOP_NOT_READY = 1,            /* serve: ticket still queued or running   */
   DOP_ERR_INVALID_ARG = -1,     /* malformed argument                      */
-  DOP_ERR_UNSUPPORTED = -2,     /* valid but not supported (e.g. M not a
-                                   power of two, M > 65536)                 */
+  DOP_ERR_UNSUPPORTED = -2,     /* valid but not supported (e.g. an M with
+                                   no plan, M > 65536)                      */
   DOP_ERR_WORKSPACE = -3,       /* workspace missing or too small          */
   DOP_ERR_DEVICE = -4,          /* HIP runtime or launch failure           */
   DOP_ERR_BUDGET = -5,          /* serve: request can never fit the arena  */
@@ -94,7 +94,10 @@ enum { DOP_OP_PROPAGATE = 0, DOP_OP_PSF = 1, DOP_OP_PSF_BACKWARD = 2 };
  */
 typedef struct {
   int32_t n;             /* DOE grid n x n, 1 <= n <= m                       */
-  int32_t m;             /* padded FFT grid m x m: power of two, 16..65536    */
+  int32_t m;             /* padded FFT grid m x m: a power of two in
+                            16..65536, or one of the grids 240, 720, 1440,
+                            3072, 3600, 28800 (= 2^7 3^2 5^2) and 40000
+                            (= 2^6 5^4, the paper's Table 2 grids)         */
   double dx;             /* sampling pitch (> 0)                              */
   double z;              /* propagation distance (any sign, 0 allowed)        */
   int32_t n_lambda;      /* K, 1..DOP_MAX_LAMBDA                              */

@@ -124,6 +124,47 @@ struct Dft<4, INV> {
   }
 };
 
+template <bool INV>
+struct Dft<3, INV> {
+  // X1,2 = a0 - (a1 + a2)/2 -/+ i (sqrt(3)/2) (a1 - a2)   (forward sign)
+  DEV static void run(float2 *a) {
+    constexpr float H = 0.866025403784438646764f;  // sin(2 pi / 3)
+    const float2 t1 = cadd(a[1], a[2]);
+    const float2 t2 = make_float2(a[0].x - 0.5f * t1.x, a[0].y - 0.5f * t1.y);
+    const float2 d = cscale(csub(a[1], a[2]), H);
+    const float2 t3 = INV ? mul_pi(d) : mul_mi(d);
+    a[0] = cadd(a[0], t1);
+    a[1] = cadd(t2, t3);
+    a[2] = csub(t2, t3);
+  }
+};
+
+template <bool INV>
+struct Dft<5, INV> {
+  // with t1 = a1 + a4, t2 = a2 + a3, t3 = a1 - a4, t4 = a2 - a3 (forward sign):
+  // X1,4 = a0 + c1 t1 + c2 t2 -/+ i (s1 t3 + s2 t4)
+  // X2,3 = a0 + c2 t1 + c1 t2 -/+ i (s2 t3 - s1 t4)
+  DEV static void run(float2 *a) {
+    constexpr float C1 = 0.309016994374947424102f;   // cos(2 pi / 5)
+    constexpr float C2 = -0.809016994374947424102f;  // cos(4 pi / 5)
+    constexpr float S1 = 0.951056516295153572116f;   // sin(2 pi / 5)
+    constexpr float S2 = 0.587785252292473129169f;   // sin(4 pi / 5)
+    const float2 t1 = cadd(a[1], a[4]), t2 = cadd(a[2], a[3]);
+    const float2 t3 = csub(a[1], a[4]), t4 = csub(a[2], a[3]);
+    const float2 r1 = make_float2(a[0].x + C1 * t1.x + C2 * t2.x, a[0].y + C1 * t1.y + C2 * t2.y);
+    const float2 r2 = make_float2(a[0].x + C2 * t1.x + C1 * t2.x, a[0].y + C2 * t1.y + C1 * t2.y);
+    const float2 q1 = make_float2(S1 * t3.x + S2 * t4.x, S1 * t3.y + S2 * t4.y);
+    const float2 q2 = make_float2(S2 * t3.x - S1 * t4.x, S2 * t3.y - S1 * t4.y);
+    const float2 i1 = INV ? mul_pi(q1) : mul_mi(q1);
+    const float2 i2 = INV ? mul_pi(q2) : mul_mi(q2);
+    a[0] = cadd(a[0], cadd(t1, t2));
+    a[1] = cadd(r1, i1);
+    a[4] = csub(r1, i1);
+    a[2] = cadd(r2, i2);
+    a[3] = csub(r2, i2);
+  }
+};
+
 // R = 4 * R2 (R = 8, 16): four-step split n = n1*R2 + n2, k = k1 + 4*k2.
 template <int R, bool INV>
 struct Dft {
@@ -154,13 +195,22 @@ struct Dft {
 };
 
 // ---------------------------------------------------------------------------
-// Stockham stage plan for an L-point DFT (L = 2..1024).
+// Stockham stage plan for an L-point DFT, L = 2^a 3^b 5^c <= 1024: the
+// power-of-two factor in radix 16/8/4 stages (as for a power-of-two L), then
+// one radix-5 stage per factor 5, then one radix-3 stage per factor 3.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+__host__ __device__ constexpr bool is_pow2c(int v) { return v > 0 && (v & (v - 1)) == 0; }
+__host__ __device__ constexpr int pow2_part(int v) { return v % 2 ? 1 : 2 * pow2_part(v / 2); }
+__host__ __device__ constexpr int count_factor(int v, int f) {
+  return v % f ? 0 : 1 + count_factor(v / f, f);
+}
 
-__host__ __device__ constexpr int num_stages(int L) { return L <= 16 ? 1 : (L <= 256 ? 2 : 3); }
+__host__ __device__ constexpr int num_stages_p2(int L) {
+  return L <= 1 ? 0 : L <= 16 ? 1 : (L <= 256 ? 2 : 3);
+}
 
-__host__ __device__ constexpr int fwd_radix(int L, int s) {
+__host__ __device__ constexpr int fwd_radix_p2(int L, int s) {
   return L <= 16 ? L
        : L == 32 ? (s == 0 ? 8 : 4)
        : L == 64 ? 8
@@ -168,6 +218,18 @@ __host__ __device__ constexpr int fwd_radix(int L, int s) {
        : L == 256 ? 16
        : L == 512 ? (s == 0 ? 16 : (s == 1 ? 8 : 4))
        : (s == 0 ? 16 : 8);  // 1024
+}
+
+__host__ __device__ constexpr int num_stages(int L) {
+  return L <= 1 ? 1
+                : num_stages_p2(pow2_part(L)) + count_factor(L, 5) + count_factor(L, 3);
+}
+
+__host__ __device__ constexpr int fwd_radix(int L, int s) {
+  return L <= 1 ? 1
+       : s < num_stages_p2(pow2_part(L))
+           ? fwd_radix_p2(pow2_part(L), s)
+           : (s - num_stages_p2(pow2_part(L)) < count_factor(L, 5) ? 5 : 3);
 }
 
 // REV reverses the radix order (used by the inverse half of the fused middle
@@ -204,10 +266,10 @@ template <class G, int R>
 DEV void decode_item(int it, int &j, int &b) {
   constexpr int LR = G::L / R;
   if constexpr (G::JFAST) {
-    j = it & (LR - 1);
+    j = is_pow2c(LR) ? it & (LR - 1) : (int)((unsigned)it % LR);
     b = it / LR;
   } else {
-    b = it & (G::NB - 1);
+    b = is_pow2c(G::NB) ? it & (G::NB - 1) : (int)((unsigned)it % G::NB);
     j = it / G::NB;
   }
 }
@@ -272,7 +334,7 @@ DEV void stages(float2 *lds, const float2 *twl, const LoadF &ld, const StoreF &s
     int j, b;
     if (live(it, j, b)) {
       if constexpr (!FIRST) {
-        const int k = j & (NS - 1);
+        const int k = is_pow2c(NS) ? j & (NS - 1) : (int)((unsigned)j % NS);
 #pragma unroll
         for (int t = 1; t < R; ++t) {
           const float2 w = twl[(t * k) * TWMUL];
@@ -312,7 +374,7 @@ DEV void stages(float2 *lds, const float2 *twl, const LoadF &ld, const StoreF &s
       const int it = tid + i * G::T;
       int j, b;
       if (live(it, j, b)) {
-        const int k = j & (NS - 1);
+        const int k = is_pow2c(NS) ? j & (NS - 1) : (int)((unsigned)j % NS);
         const int base = (j - k) * R + k;
 #pragma unroll
         for (int t = 0; t < R; ++t) lds[(base + t * NS) * G::SJ + b * G::SB] = v[i][t];
@@ -374,68 +436,118 @@ struct NoStore {
 };
 
 // ---------------------------------------------------------------------------
-// Pass plan per log2(M).  Tiles of passes B and C hold at most 8192 points
-// (64 KiB + padding), so two blocks fit in one CU's 160 KiB LDS; tiles of
-// passes A and A' hold up to 16384 (one block per CU) so that every row run
-// they move is a whole 128-byte line.
+// Pass plans.  Tiles of passes B and C hold at most 8192 points (64 KiB +
+// padding), so two blocks fit in one CU's 160 KiB LDS; tiles of passes A and
+// A' hold up to 16384 (one block per CU) so that every row run they move is a
+// whole 128-byte line.
+//
+// Plan id PID < kNp2Base: M = 2^PID.  PID = kNp2Base + i: the i-th grid of
+// np2_plan, M = 2^a 3^b 5^c with a hand-chosen digit split (AX, BX, AY, BY):
+// BX a power of two >= 16, every tile within the limits above, and every
+// digit length a product of the radices 16/8/4/2, 5 and 3.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 __host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
+__host__ __device__ constexpr int round64(int v) { return (v + 63) / 64 * 64; }
 __host__ __device__ constexpr int plan_bx(int lm) { return cmin(lm / 2, 6); }
 __host__ __device__ constexpr int plan_ay(int lm) {
   return cmin(cmin(lm / 2, 7), 13 - plan_bx(lm));
 }
-__host__ __device__ constexpr int threads_for(int pts) { return cmin(512, cmax(64, pts / 16)); }
+__host__ __device__ constexpr int threads_for(int pts) {
+  return round64(cmin(512, cmax(64, pts / 16)));
+}
+
+struct Np2Plan {
+  int m, ax, bx, ay, by;
+};
+constexpr int kNp2Base = 100;
+constexpr int kNumNp2 = 7;
+__host__ __device__ constexpr Np2Plan np2_plan(int i) {
+  return i == 0   ? Np2Plan{240, 15, 16, 15, 16}
+         : i == 1 ? Np2Plan{720, 45, 16, 45, 16}
+         : i == 2 ? Np2Plan{1440, 45, 32, 45, 32}
+         : i == 3 ? Np2Plan{3072, 48, 64, 48, 64}
+         : i == 4 ? Np2Plan{3600, 225, 16, 15, 240}
+         : i == 5 ? Np2Plan{28800, 450, 64, 60, 480}    // 2^7 3^2 5^2
+         : i == 6 ? Np2Plan{40000, 625, 64, 100, 400}   // 2^6 5^4
+                  : Np2Plan{0, 0, 0, 0, 0};
+}
 
 // Two 512-thread blocks per CU = 4 waves per SIMD: caps registers at 128.
 #define DOP_KERNEL(T) __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4)))
 
-template <int LOGM>
+template <int PID>
 struct Plan {
-  static constexpr int M = 1 << LOGM;
+  static constexpr bool POW2 = PID < kNp2Base;
+  static constexpr Np2Plan NP = np2_plan(POW2 ? -1 : PID - kNp2Base);
+  static constexpr int M = POW2 ? 1 << PID : NP.m;
   static constexpr size_t PITCH = (size_t)M + kRowPad;  // workspace row pitch
-  static constexpr int BX = 1 << plan_bx(LOGM);
+  static constexpr int BX = POW2 ? 1 << plan_bx(PID) : NP.bx;
   static constexpr int AX = M / BX;
-  static constexpr int AY = 1 << plan_ay(LOGM);
+  static constexpr int AY = POW2 ? 1 << plan_ay(PID) : NP.ay;
   static constexpr int BY = M / AY;
   static constexpr int RA = cmin(16, BX);  // contiguous run in passes A / A': a 128-byte line
   static constexpr int RC = cmin(16, M);   // contiguous run in pass C
   // A / A' tiles (up to 1024 x 16 points, 128 KiB of LDS) run one block of
   // up to 1024 threads per CU
-  static constexpr int TA = cmin(1024, cmax(64, AX * RA / 16));
+  static constexpr int TA = round64(cmin(1024, cmax(64, AX * RA / 16)));
   static constexpr int TB = threads_for(BX * AY);
   static constexpr int TC = threads_for(BY * RC);
   // Twiddles in LDS: omega_M^q = HI[q / S] * LO[q % S] with HI[i] = omega_M^(i S)
-  // (= omega_THI^i, which also serves every inner DFT length L <= THI) and
-  // LO[i] = omega_M^i.
-  static constexpr int THI = M < 1024 ? M : 1024;
+  // (= omega_THI^i) and LO[i] = omega_M^i.  Power-of-two M: THI = min(M, 1024),
+  // which also serves every inner DFT length.  Other M: THI = AX (S = BX), the
+  // inner table of passes A and A'; passes B, B' and C keep their own.
+  static constexpr int THI = POW2 ? (M < 1024 ? M : 1024) : AX;
   static constexpr int S = M / THI;
   static constexpr int LOGS = ilog2c(S);
+  static_assert(AX * BX == M && AY * BY == M, "digit split");
+  static_assert(is_pow2c(BX) && BX % RA == 0 && M % RC == 0, "runs");
+  static_assert(AX * RA <= 16384 && BX * AY <= 8192 && BY * RC <= 8192, "tile sizes");
+  static_assert(AX <= 1024 && BX <= 1024 && AY <= 1024 && BY <= 1024, "digit lengths");
 };
 
-template <int LOGM>
+template <int PID>
 struct TwLds {
-  float2 hi[Plan<LOGM>::THI];
-  float2 lo[Plan<LOGM>::S];
+  float2 hi[Plan<PID>::THI];
+  float2 lo[Plan<PID>::S];
 };
 
-// Copy this plan's twiddles from the FP64-generated global table into LDS.
-template <int LOGM, int T>
-DEV void tw_fill(TwLds<LOGM> &t, const float2 *__restrict__ g) {
-  using P = Plan<LOGM>;
-  for (int i = threadIdx.x; i < P::THI; i += T) t.hi[i] = g[(i * P::S) << (kTwLog - LOGM)];
-  for (int i = threadIdx.x; i < P::S; i += T) t.lo[i] = g[i << (kTwLog - LOGM)];
+// exp(-2 pi i num / den), 0 <= num < den, formed in FP64 and rounded once.
+DEV float2 omega_fp64(int num, int den) {
+  double sn, cs;
+  sincospi(-2.0 * (double)num / (double)den, &sn, &cs);
+  return make_float2((float)cs, (float)sn);
 }
 
-// omega_M^q (forward sign).
-template <int LOGM>
-DEV float2 tw_q(const TwLds<LOGM> &t, int q) {
-  using P = Plan<LOGM>;
-  q &= P::M - 1;
-  if constexpr (P::S == 1) {
-    return t.hi[q];
+// This plan's twiddles in LDS: from the FP64-generated global table
+// (power-of-two M), or generated in FP64 (other M).
+template <int PID, int T>
+DEV void tw_fill(TwLds<PID> &t, const float2 *__restrict__ g) {
+  using P = Plan<PID>;
+  if constexpr (P::POW2) {
+    for (int i = threadIdx.x; i < P::THI; i += T) t.hi[i] = g[(i * P::S) << (kTwLog - PID)];
+    for (int i = threadIdx.x; i < P::S; i += T) t.lo[i] = g[i << (kTwLog - PID)];
   } else {
-    return cmul(t.hi[q >> P::LOGS], t.lo[q & (P::S - 1)]);
+    for (int i = threadIdx.x; i < P::THI; i += T) t.hi[i] = omega_fp64(i * P::S, P::M);
+    for (int i = threadIdx.x; i < P::S; i += T) t.lo[i] = omega_fp64(i, P::M);
+  }
+}
+
+// Table of omega_L^i, i < L (the inner twiddles of an L-point DFT).
+template <int L, int T>
+DEV void omega_fill(float2 *t) {
+  for (int i = threadIdx.x; i < L; i += T) t[i] = omega_fp64(i, L);
+}
+
+// omega_M^q (forward sign), q >= 0.
+template <int PID>
+DEV float2 tw_q(const TwLds<PID> &t, int q) {
+  using P = Plan<PID>;
+  const unsigned u = (unsigned)q % (unsigned)P::M;
+  if constexpr (P::S == 1) {
+    return t.hi[u];
+  } else {
+    return cmul(t.hi[u / P::S], t.lo[u % P::S]);
   }
 }
 
@@ -547,15 +659,15 @@ DEV const T *at_byte(const T *base, unsigned off) {
 // Pass A: DFT over xa for the N input rows, input formed on the fly.
 // Tile = one row y and a run of RA consecutive xb.
 // ---------------------------------------------------------------------------
-template <int LOGM, int INM>
-DOP_KERNEL(Plan<LOGM>::TA) void k_pass_a_fwd(KParams p) {
-  using P = Plan<LOGM>;
+template <int PID, int INM>
+DOP_KERNEL(Plan<PID>::TA) void k_pass_a_fwd(KParams p) {
+  using P = Plan<PID>;
   constexpr int AX = P::AX, BX = P::BX, RA = P::RA, T = P::TA;
   using G = Geo<AX, RA, RA, 1, T, false>;
   using FS = FirstStage<G>;
   __shared__ float2 lds[AX * RA];
-  __shared__ TwLds<LOGM> tw;
-  tw_fill<LOGM, T>(tw, p.tw);
+  __shared__ TwLds<PID> tw;
+  tw_fill<PID, T>(tw, p.tw);
   constexpr int RUNS = BX / RA;
   const int ntiles = p.nrows_in * RUNS;
   const int n = p.n;
@@ -629,7 +741,7 @@ DOP_KERNEL(Plan<LOGM>::TA) void k_pass_a_fwd(KParams p) {
     float2 *out = p.ws + (size_t)y * P::PITCH;
     auto st = [&](int kxa, int b, float2 w) {
       const int xb = xb0 + b;
-      out[BX * kxa + xb] = cmul(w, tw_q<LOGM>(tw, xb * kxa));
+      out[BX * kxa + xb] = cmul(w, tw_q<PID>(tw, xb * kxa));
     };
     dft_tile<G, false, false, SRC_REG, SNK_FN, P::THI>(lds, tw.hi, NoLoad{}, st, v, tid);
   }
@@ -646,17 +758,26 @@ DEV void st_pair(float2 *p, float2 a, float2 b) {
   *reinterpret_cast<f4v *>(p) = f4v{a.x, a.y, b.x, b.y};
 }
 
-template <int LOGM>
-DOP_KERNEL(Plan<LOGM>::TB) void k_pass_b_fwd(KParams p) {
-  using P = Plan<LOGM>;
+template <int PID>
+DOP_KERNEL(Plan<PID>::TB) void k_pass_b_fwd(KParams p) {
+  using P = Plan<PID>;
   constexpr int AX = P::AX, BX = P::BX, AY = P::AY, BY = P::BY, T = P::TB;
   constexpr int SR = BX + 1;  // odd row stride: conflict-free for both DFT directions
   constexpr int HB = BX / 2;  // 16-byte pairs per row segment
   constexpr int PF = (AY * HB + T - 1) / T;  // pairs each thread moves per tile
   __shared__ float2 lds[AY * SR];
-  __shared__ TwLds<LOGM> tw;
+  __shared__ TwLds<PID> tw;
   __shared__ float2 rowtw[AY];
-  tw_fill<LOGM, T>(tw, p.tw);
+  // inner twiddles: the shared power-of-two table, else tables of their own
+  __shared__ float2 wbx[P::POW2 ? 1 : BX], way[P::POW2 ? 1 : AY];
+  tw_fill<PID, T>(tw, p.tw);
+  if constexpr (!P::POW2) {
+    omega_fill<BX, T>(wbx);
+    omega_fill<AY, T>(way);
+  }
+  constexpr int THX = P::POW2 ? P::THI : BX, THY = P::POW2 ? P::THI : AY;
+  const float2 *twx = P::POW2 ? tw.hi : wbx;
+  const float2 *twy = P::POW2 ? tw.hi : way;
   constexpr int NT = AX * BY;
   float2 dummy[1][1];
   // rows ya with BY*ya + yb >= nrows_in hold zeros: not read, x-DFT skipped
@@ -687,7 +808,7 @@ DOP_KERNEL(Plan<LOGM>::TB) void k_pass_b_fwd(KParams p) {
     const size_t col0 = (size_t)BX * kxa;
     const int nz = nzrows(yb);
     __syncthreads();
-    for (int r = tid; r < AY; r += T) rowtw[r] = tw_q<LOGM>(tw, yb * r);  // omega_M^(yb kya)
+    for (int r = tid; r < AY; r += T) rowtw[r] = tw_q<PID>(tw, yb * r);  // omega_M^(yb kya)
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
       const int e = tid + i * T, ya = e / HB, c = e % HB;
@@ -699,10 +820,9 @@ DOP_KERNEL(Plan<LOGM>::TB) void k_pass_b_fwd(KParams p) {
     if (pt + (int)gridDim.x < NT) fetch(pt + gridDim.x, tid);
     __syncthreads();
     using GX = Geo<BX, AY, 1, SR, T, false>;
-    dft_tile<GX, false, false, SRC_LDS, SNK_LDS, P::THI>(lds, tw.hi, NoLoad{}, NoStore{}, dummy, tid,
-                                                        nz);
+    dft_tile<GX, false, false, SRC_LDS, SNK_LDS, THX>(lds, twx, NoLoad{}, NoStore{}, dummy, tid, nz);
     using GY = Geo<AY, BX, SR, 1, T, false>;
-    dft_tile<GY, false, false, SRC_LDS, SNK_LDS, P::THI>(lds, tw.hi, NoLoad{}, NoStore{}, dummy, tid);
+    dft_tile<GY, false, false, SRC_LDS, SNK_LDS, THY>(lds, twy, NoLoad{}, NoStore{}, dummy, tid);
     for (int e = tid; e < AY * HB; e += T) {
       const int kya = e / HB, c = e % HB;
       const float2 w = rowtw[kya];
@@ -716,9 +836,9 @@ DOP_KERNEL(Plan<LOGM>::TB) void k_pass_b_fwd(KParams p) {
 // Pass C: DFT over yb, times H, inverse DFT over yb (tile = (kya, run of RC
 // columns)).
 // ---------------------------------------------------------------------------
-template <int LOGM>
-DOP_KERNEL(Plan<LOGM>::TC) void k_pass_c(KParams p) {
-  using P = Plan<LOGM>;
+template <int PID>
+DOP_KERNEL(Plan<PID>::TC) void k_pass_c(KParams p) {
+  using P = Plan<PID>;
   constexpr int AX = P::AX, BX = P::BX, AY = P::AY, BY = P::BY, M = P::M, RC = P::RC, T = P::TC;
   using G = Geo<BY, RC, RC + 1, 1, T, false>;
   using FS = FirstStage<G>;
@@ -728,7 +848,11 @@ DOP_KERNEL(Plan<LOGM>::TC) void k_pass_c(KParams p) {
   __shared__ float2 twc[BY];
   // a2_eff of the tile's BY frequency rows
   __shared__ double a2row[BY];
-  for (int i = threadIdx.x; i < BY; i += T) twc[i] = p.tw[i << (kTwLog - ilog2c(BY))];
+  if constexpr (P::POW2) {
+    for (int i = threadIdx.x; i < BY; i += T) twc[i] = p.tw[i << (kTwLog - ilog2c(BY))];
+  } else {
+    omega_fill<BY, T>(twc);
+  }
   constexpr int RUNS = M / RC;
   constexpr int NT = AY * RUNS;
   using LR_ = LastRegs<G, false>;
@@ -804,17 +928,25 @@ DOP_KERNEL(Plan<LOGM>::TC) void k_pass_c(KParams p) {
 // Pass B': inverse DFT over kya then over kxb (tile = (kxa, yb)); writes the
 // rows y < nrows_out.
 // ---------------------------------------------------------------------------
-template <int LOGM>
-DOP_KERNEL(Plan<LOGM>::TB) void k_pass_b_inv(KParams p) {
-  using P = Plan<LOGM>;
+template <int PID>
+DOP_KERNEL(Plan<PID>::TB) void k_pass_b_inv(KParams p) {
+  using P = Plan<PID>;
   constexpr int AX = P::AX, BX = P::BX, AY = P::AY, BY = P::BY, T = P::TB;
   constexpr int SR = BX + 1;
   constexpr int HB = BX / 2;
   constexpr int PF = (AY * HB + T - 1) / T;
   __shared__ float2 lds[AY * SR];
-  __shared__ TwLds<LOGM> tw;
+  __shared__ TwLds<PID> tw;
   __shared__ float2 rowtw[AY];
-  tw_fill<LOGM, T>(tw, p.tw);
+  __shared__ float2 wbx[P::POW2 ? 1 : BX], way[P::POW2 ? 1 : AY];
+  tw_fill<PID, T>(tw, p.tw);
+  if constexpr (!P::POW2) {
+    omega_fill<BX, T>(wbx);
+    omega_fill<AY, T>(way);
+  }
+  constexpr int THX = P::POW2 ? P::THI : BX, THY = P::POW2 ? P::THI : AY;
+  const float2 *twx = P::POW2 ? tw.hi : wbx;
+  const float2 *twy = P::POW2 ? tw.hi : way;
   constexpr int NT = AX * BY;
   float2 dummy[1][1];
   f4v pre[PF];
@@ -838,7 +970,7 @@ DOP_KERNEL(Plan<LOGM>::TB) void k_pass_b_inv(KParams p) {
     // only the rows ya with BY*ya + yb < nrows_out are needed
     const int nz = p.nrows_out > yb ? cmin(AY, (p.nrows_out - yb + BY - 1) / BY) : 0;
     __syncthreads();
-    for (int r = tid; r < AY; r += T) rowtw[r] = tw_q<LOGM>(tw, yb * r);
+    for (int r = tid; r < AY; r += T) rowtw[r] = tw_q<PID>(tw, yb * r);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
@@ -852,10 +984,9 @@ DOP_KERNEL(Plan<LOGM>::TB) void k_pass_b_inv(KParams p) {
     if (pt + (int)gridDim.x < NT) fetch(pt + gridDim.x, tid);
     __syncthreads();
     using GY = Geo<AY, BX, SR, 1, T, false>;
-    dft_tile<GY, true, false, SRC_LDS, SNK_LDS, P::THI>(lds, tw.hi, NoLoad{}, NoStore{}, dummy, tid);
+    dft_tile<GY, true, false, SRC_LDS, SNK_LDS, THY>(lds, twy, NoLoad{}, NoStore{}, dummy, tid);
     using GX = Geo<BX, AY, 1, SR, T, false>;
-    dft_tile<GX, true, false, SRC_LDS, SNK_LDS, P::THI>(lds, tw.hi, NoLoad{}, NoStore{}, dummy, tid,
-                                                       nz);
+    dft_tile<GX, true, false, SRC_LDS, SNK_LDS, THX>(lds, twx, NoLoad{}, NoStore{}, dummy, tid, nz);
     for (int e = tid; e < nz * HB; e += T) {
       const int ya = e / HB, c = e % HB;
       st_pair(p.ws + (size_t)(BY * ya + yb) * P::PITCH + col0 + 2 * c, lds[ya * SR + 2 * c],
@@ -868,9 +999,9 @@ DOP_KERNEL(Plan<LOGM>::TB) void k_pass_b_inv(KParams p) {
 // Pass A': inverse DFT over kxa for the rows y < nrows_out, then the output
 // stage: PSF accumulation (Eq. 4), field, or height gradient.
 // ---------------------------------------------------------------------------
-template <int LOGM, int OUTM>
-DOP_KERNEL(Plan<LOGM>::TA) void k_pass_a_inv(KParams p) {
-  using P = Plan<LOGM>;
+template <int PID, int OUTM>
+DOP_KERNEL(Plan<PID>::TA) void k_pass_a_inv(KParams p) {
+  using P = Plan<PID>;
   constexpr int AX = P::AX, BX = P::BX, RA = P::RA, M = P::M, T = P::TA;
   using G = Geo<AX, RA, RA, 1, T, false>;
   using FS = FirstStage<G>;
@@ -878,8 +1009,8 @@ DOP_KERNEL(Plan<LOGM>::TA) void k_pass_a_inv(KParams p) {
   constexpr int LRL = AX / LS::R;
   using SSL = StageShape<G, LS::R>;
   __shared__ float2 lds[AX * RA];
-  __shared__ TwLds<LOGM> tw;
-  tw_fill<LOGM, T>(tw, p.tw);
+  __shared__ TwLds<PID> tw;
+  tw_fill<PID, T>(tw, p.tw);
   constexpr int RUNS = BX / RA;
   const int ntiles = p.nrows_out * RUNS;
   const int n = p.n;
@@ -903,7 +1034,8 @@ DOP_KERNEL(Plan<LOGM>::TA) void k_pass_a_inv(KParams p) {
   auto out_index = [&](int y, int xb0, int xa, int b) -> long long {
     const int x = BX * xa + xb0 + b;
     if (p.full) {
-      const int yo = (y + p.p0) & (M - 1), xo = (x + p.p0) & (M - 1);
+      const int ys = y + p.p0, xs = x + p.p0;  // both < 2M
+      const int yo = ys >= M ? ys - M : ys, xo = xs >= M ? xs - M : xs;
       return (long long)yo * M + xo;
     }
     return x < n ? (long long)y * n + x : -1;
@@ -928,7 +1060,7 @@ DOP_KERNEL(Plan<LOGM>::TA) void k_pass_a_inv(KParams p) {
         decode_item<G, FS::R>(it, j, b);
 #pragma unroll
         for (int t = 0; t < FS::R; ++t)
-          v[i][t] = cmulc(pre[i][t], tw_q<LOGM>(tw, (xb0 + b) * (j + t * FS::LR)));
+          v[i][t] = cmulc(pre[i][t], tw_q<PID>(tw, (xb0 + b) * (j + t * FS::LR)));
       }
     }
     // After the first stage: read the accumulator values this tile will add
@@ -993,9 +1125,9 @@ static inline void mark(hipEvent_t *ev, int i, hipStream_t s) {
   if (ev) (void)hipEventRecord(ev[i], s);
 }
 
-template <int LOGM>
+template <int PID>
 static hipError_t launch_impl(const KParams &p, hipStream_t s, hipEvent_t *ev) {
-  using P = Plan<LOGM>;
+  using P = Plan<PID>;
   auto grid = [](long long tiles) {
     return (unsigned)(tiles < kMaxBlocks ? tiles : kMaxBlocks);
   };
@@ -1005,30 +1137,30 @@ static hipError_t launch_impl(const KParams &p, hipStream_t s, hipEvent_t *ev) {
   const unsigned gai = grid((long long)p.nrows_out * (P::BX / P::RA));
   mark(ev, 0, s);
   if (p.in_mode == IN_PHASE)
-    hipLaunchKernelGGL((k_pass_a_fwd<LOGM, IN_PHASE>), dim3(ga), dim3(P::TA), 0, s, p);
+    hipLaunchKernelGGL((k_pass_a_fwd<PID, IN_PHASE>), dim3(ga), dim3(P::TA), 0, s, p);
   else if (p.in_mode == IN_FIELD)
-    hipLaunchKernelGGL((k_pass_a_fwd<LOGM, IN_FIELD>), dim3(ga), dim3(P::TA), 0, s, p);
+    hipLaunchKernelGGL((k_pass_a_fwd<PID, IN_FIELD>), dim3(ga), dim3(P::TA), 0, s, p);
   else
-    hipLaunchKernelGGL((k_pass_a_fwd<LOGM, IN_GRAD>), dim3(ga), dim3(P::TA), 0, s, p);
+    hipLaunchKernelGGL((k_pass_a_fwd<PID, IN_GRAD>), dim3(ga), dim3(P::TA), 0, s, p);
   mark(ev, 1, s);
-  hipLaunchKernelGGL(k_pass_b_fwd<LOGM>, dim3(gb), dim3(P::TB), 0, s, p);
+  hipLaunchKernelGGL(k_pass_b_fwd<PID>, dim3(gb), dim3(P::TB), 0, s, p);
   mark(ev, 2, s);
-  hipLaunchKernelGGL(k_pass_c<LOGM>, dim3(gc), dim3(P::TC), 0, s, p);
+  hipLaunchKernelGGL(k_pass_c<PID>, dim3(gc), dim3(P::TC), 0, s, p);
   mark(ev, 3, s);
-  hipLaunchKernelGGL(k_pass_b_inv<LOGM>, dim3(gb), dim3(P::TB), 0, s, p);
+  hipLaunchKernelGGL(k_pass_b_inv<PID>, dim3(gb), dim3(P::TB), 0, s, p);
   mark(ev, 4, s);
   if (p.out_mode == OUT_PSF)
-    hipLaunchKernelGGL((k_pass_a_inv<LOGM, OUT_PSF>), dim3(gai), dim3(P::TA), 0, s, p);
+    hipLaunchKernelGGL((k_pass_a_inv<PID, OUT_PSF>), dim3(gai), dim3(P::TA), 0, s, p);
   else if (p.out_mode == OUT_FIELD)
-    hipLaunchKernelGGL((k_pass_a_inv<LOGM, OUT_FIELD>), dim3(gai), dim3(P::TA), 0, s, p);
+    hipLaunchKernelGGL((k_pass_a_inv<PID, OUT_FIELD>), dim3(gai), dim3(P::TA), 0, s, p);
   else
-    hipLaunchKernelGGL((k_pass_a_inv<LOGM, OUT_GRADH>), dim3(gai), dim3(P::TA), 0, s, p);
+    hipLaunchKernelGGL((k_pass_a_inv<PID, OUT_GRADH>), dim3(gai), dim3(P::TA), 0, s, p);
   mark(ev, 5, s);
   return hipGetLastError();
 }
 
 hipError_t launch_wavelength(const KParams &p, hipStream_t s, hipEvent_t *ev) {
-  switch (p.logm) {
+  switch (p.plan) {
     case 4: return launch_impl<4>(p, s, ev);
     case 5: return launch_impl<5>(p, s, ev);
     case 6: return launch_impl<6>(p, s, ev);
@@ -1042,19 +1174,39 @@ hipError_t launch_wavelength(const KParams &p, hipStream_t s, hipEvent_t *ev) {
     case 14: return launch_impl<14>(p, s, ev);
     case 15: return launch_impl<15>(p, s, ev);
     case 16: return launch_impl<16>(p, s, ev);
+    case kNp2Base + 0: return launch_impl<kNp2Base + 0>(p, s, ev);
+    case kNp2Base + 1: return launch_impl<kNp2Base + 1>(p, s, ev);
+    case kNp2Base + 2: return launch_impl<kNp2Base + 2>(p, s, ev);
+    case kNp2Base + 3: return launch_impl<kNp2Base + 3>(p, s, ev);
+    case kNp2Base + 4: return launch_impl<kNp2Base + 4>(p, s, ev);
+    case kNp2Base + 5: return launch_impl<kNp2Base + 5>(p, s, ev);
+    case kNp2Base + 6: return launch_impl<kNp2Base + 6>(p, s, ev);
     default: return hipErrorInvalidValue;
   }
 }
+static_assert(kNumNp2 == 7, "one launch case per grid of np2_plan");
 
-template <int LOGM>
+int plan_id(int m) {
+  if (m >= 16 && m <= 65536 && is_pow2c(m)) return ilog2c(m);
+  for (int i = 0; i < kNumNp2; ++i)
+    if (np2_plan(i).m == m) return kNp2Base + i;
+  return -1;
+}
+
+int np2_grids(int *out, int max) {
+  for (int i = 0; i < kNumNp2 && i < max; ++i) out[i] = np2_plan(i).m;
+  return kNumNp2;
+}
+
+template <int PID>
 static void fill_plan(PlanInfo *o) {
-  using P = Plan<LOGM>;
+  using P = Plan<PID>;
   o->ax = P::AX; o->bx = P::BX; o->ay = P::AY; o->by = P::BY; o->ra = P::RA; o->rc = P::RC;
   o->threads_a = P::TA; o->threads_b = P::TB; o->threads_c = P::TC;
 }
 
-bool plan_info(int logm, PlanInfo *o) {
-  switch (logm) {
+bool plan_info(int plan, PlanInfo *o) {
+  switch (plan) {
     case 4: fill_plan<4>(o); return true;
     case 5: fill_plan<5>(o); return true;
     case 6: fill_plan<6>(o); return true;
@@ -1068,6 +1220,13 @@ bool plan_info(int logm, PlanInfo *o) {
     case 14: fill_plan<14>(o); return true;
     case 15: fill_plan<15>(o); return true;
     case 16: fill_plan<16>(o); return true;
+    case kNp2Base + 0: fill_plan<kNp2Base + 0>(o); return true;
+    case kNp2Base + 1: fill_plan<kNp2Base + 1>(o); return true;
+    case kNp2Base + 2: fill_plan<kNp2Base + 2>(o); return true;
+    case kNp2Base + 3: fill_plan<kNp2Base + 3>(o); return true;
+    case kNp2Base + 4: fill_plan<kNp2Base + 4>(o); return true;
+    case kNp2Base + 5: fill_plan<kNp2Base + 5>(o); return true;
+    case kNp2Base + 6: fill_plan<kNp2Base + 6>(o); return true;
     default: return false;
   }
 }

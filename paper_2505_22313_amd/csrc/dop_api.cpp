@@ -56,9 +56,14 @@ dop_status validate_problem(const dop_problem *prob) {
   if (!prob) return fail(DOP_ERR_INVALID_ARG, "problem is NULL");
   if (prob->n < 1) return fail(DOP_ERR_INVALID_ARG, "n must be >= 1 (got %d)", prob->n);
   if (prob->m < 1) return fail(DOP_ERR_INVALID_ARG, "m must be >= 1 (got %d)", prob->m);
-  if (!is_pow2(prob->m) || prob->m < DOP_MIN_M || prob->m > DOP_MAX_M)
-    return fail(DOP_ERR_UNSUPPORTED, "m must be a power of two in [%d, %d] (got %d)", DOP_MIN_M,
-                DOP_MAX_M, prob->m);
+  if (plan_id(prob->m) < 0) {
+    int g[16];
+    const int ng = np2_grids(g, 16);
+    std::string list;
+    for (int i = 0; i < ng && i < 16; ++i) list += (i ? ", " : "") + std::to_string(g[i]);
+    return fail(DOP_ERR_UNSUPPORTED, "m must be a power of two in [%d, %d] or one of %s (got %d)",
+                DOP_MIN_M, DOP_MAX_M, list.c_str(), prob->m);
+  }
   if (prob->n > prob->m) return fail(DOP_ERR_INVALID_ARG, "n (%d) exceeds m (%d)", prob->n, prob->m);
   if (!(prob->dx > 0.0) || !std::isfinite(prob->dx))
     return fail(DOP_ERR_INVALID_ARG, "dx must be finite and > 0");
@@ -127,7 +132,7 @@ void fill_common(KParams &kp, const dop_context *ctx, const dop_problem *prob, i
   kp.tw = ctx->tw;
   kp.n = prob->n;
   kp.m = prob->m;
-  kp.logm = ilog2i(prob->m);
+  kp.plan = plan_id(prob->m);
   kp.nrows_in = prob->n;
   kp.p0 = (prob->m - prob->n) / 2;
   kp.up_log2 = ilog2i(upsample_factor(prob));

@@ -35,7 +35,7 @@ enum OutMode : int {
 struct KParams {
   float2 *ws;            // M x M c64 workspace
   const float2 *tw;      // twiddle table, kTwN entries
-  int n, m, logm;
+  int n, m, plan;         // plan id of M (plan_id)
   int nrows_in;          // rows of the padded input that may be nonzero
   int nrows_out;         // rows of the output plane that are needed
   int p0;                // (M - N) / 2
@@ -73,13 +73,22 @@ constexpr int kNumPasses = 5;
 // after the last one.
 hipError_t launch_wavelength(const KParams &p, hipStream_t stream, hipEvent_t *ev);
 
-// Tile geometry of the pass plan for a given log2(M) (host-side copy of the
-// compile-time plan, used for reporting and tests).
+// Plan id of grid size M: log2(M) for a power of two in [16, 65536], a
+// larger id for each supported grid that is not a power of two, -1 if M has
+// no plan.
+int plan_id(int m);
+
+// The supported grids that are not powers of two: writes up to `max` sizes
+// and returns how many there are.
+int np2_grids(int *out, int max);
+
+// Tile geometry of a pass plan (host-side copy of the compile-time plan,
+// used for reporting and tests).
 struct PlanInfo {
   int ax, bx, ay, by, ra, rc;
   int threads_a, threads_b, threads_c;
 };
-bool plan_info(int logm, PlanInfo *out);
+bool plan_info(int plan, PlanInfo *out);
 
 // Super-resolved front end: fine = W coarse W^T and its adjoint (kind 0:
 // nearest, 1: Lanczos-3; see dop_upsample).  Arguments already validated.

@@ -53,7 +53,7 @@ def good(**kw):
 
 
 def test_workspace_size_valid():
-    for m in [16, 1024, 65536]:
+    for m in [16, 1024, 65536, 240, 720, 1440, 3072, 3600, 28800, 40000]:
         st, b = _ws(good(n=m // 2, m=m))
         assert st == L.DOP_OK and b == 8 * m * (m + 16)
     for op in (L.DOP_OP_PROPAGATE, L.DOP_OP_PSF, L.DOP_OP_PSF_BACKWARD):
@@ -61,7 +61,9 @@ def test_workspace_size_valid():
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(m=1000), L.DOP_ERR_UNSUPPORTED),          # not a power of two
+    (dict(m=1000), L.DOP_ERR_UNSUPPORTED),          # not a supported grid
+    (dict(m=30000, n=100), L.DOP_ERR_UNSUPPORTED),   # 2^4 3 5^4: no plan
+    (dict(m=2 * 28800, n=100), L.DOP_ERR_UNSUPPORTED),
     (dict(m=131072, n=100), L.DOP_ERR_UNSUPPORTED),  # beyond 65536
     (dict(m=8, n=4), L.DOP_ERR_UNSUPPORTED),         # below the minimum
     (dict(n=2048), L.DOP_ERR_INVALID_ARG),           # n > m

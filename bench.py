@@ -239,6 +239,30 @@ def variants_measure(api, wl, torch, p, hd, ctx, base_ms):
         "adjoint_ms": round(ms_adj, 3), "adjoint_alg_gbs": round(nbytes / (ms_adj * 1e-3) / 1e9, 1),
         "share_of_step": round((ms_up + ms_adj) / base_ms, 5), "n_lambda": k}
     del fine, gc, hc
+    torch.cuda.empty_cache()
+    # the paper's own grids that are not powers of two (Table 2), 6 wavelengths
+    lams6 = np.linspace(0.4, 0.7, 6)
+    grids = {}
+    for m_, dx_ in ((28800, 0.25), (40000, 0.25)):
+        n_ = m_ // 2
+        hg = torch.rand((n_, n_), generator=torch.Generator(device="cuda").manual_seed(m_),
+                        device="cuda") * 1.2
+        pg = api.Problem(n_, m_, dx_, p["z"], lams6, wl.cauchy_index(lams6))
+        og = torch.empty((n_, n_), dtype=torch.float32, device="cuda")
+        ctx.profile_enable(True)
+        ms = _event_ms(torch, lambda: api.psf(hg, pg, out=og, ctx=ctx), 2)
+        prof = ctx.profile_read()
+        ctx.profile_enable(False)
+        pb = pass_bytes(n_, m_, k_first=False)
+        grids[str(m_)] = {
+            "n": n_, "n_lambda": 6, "ms_per_step": round(ms, 2),
+            "value": round(6 * float(m_) * m_ / (ms * 1e-3) / 1e6, 1),
+            "passes_alg_gbs": {k: round(pb[k] / (v[1] / v[0] * 1e-3) / 1e9, 1)
+                               for k, v in prof.items()}}
+        del hg, og
+        ctx.release_workspaces()
+        torch.cuda.empty_cache()
+    res["np2_grids"] = grids
     return res
 
 

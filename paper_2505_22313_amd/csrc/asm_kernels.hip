@@ -490,9 +490,11 @@ struct Plan {
   static constexpr int RC = cmin(16, M);   // contiguous run in pass C
   // A / A' tiles (up to 1024 x 16 points, 128 KiB of LDS) run one block of
   // up to 1024 threads per CU
-  static constexpr int TA = round64(cmin(1024, cmax(64, AX * RA / 16)));
-  static constexpr int TB = threads_for(BX * AY);
-  static constexpr int TC = threads_for(BY * RC);
+  // (other M: about 8 points per thread, since their mixed-radix stage
+  // shapes do not divide evenly among threads and need more registers each)
+  static constexpr int TA = round64(cmin(1024, cmax(64, AX * RA / (POW2 ? 16 : 8))));
+  static constexpr int TB = POW2 ? threads_for(BX * AY) : round64(cmin(1024, cmax(64, BX * AY / 8)));
+  static constexpr int TC = POW2 ? threads_for(BY * RC) : round64(cmin(1024, cmax(64, BY * RC / 8)));
   // Twiddles in LDS: omega_M^q = HI[q / S] * LO[q % S] with HI[i] = omega_M^(i S)
   // (= omega_THI^i) and LO[i] = omega_M^i.  Power-of-two M: THI = min(M, 1024),
   // which also serves every inner DFT length.  Other M: THI = AX (S = BX), the

@@ -200,6 +200,28 @@ def copy_ceiling_gbs(torch, nbytes=1 << 32):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
+def other_workloads_measure(api, wl, torch, ctx):
+    """The small (512^2 -> 1024^2, 1 wavelength, launch-bound) and mid
+    (8192^2 -> 16384^2, 3 wavelengths) workloads: time per PSF call."""
+    res = {}
+    for name, reps in (("small", 200), ("mid", 5)):
+        q = wl.problem(name)
+        prob = api.Problem.from_dict(q)
+        h = torch.from_numpy(wl.heights(name)).cuda()
+        out = torch.empty((q["n"], q["n"]), dtype=torch.float32, device="cuda")
+        ms = _event_ms(torch, lambda: api.psf(h, prob, out=out, ctx=ctx), reps)
+        k = len(q["lams"])
+        step = sum(pass_bytes(q["n"], q["m"], True).values()) + \
+            (k - 1) * sum(pass_bytes(q["n"], q["m"], False).values())
+        res[name] = {"n": q["n"], "m": q["m"], "n_lambda": k, "us_per_call": round(ms * 1e3, 1),
+                     "value": round(k * float(q["m"]) ** 2 / (ms * 1e-3) / 1e6, 1),
+                     "alg_gbs": round(step / (ms * 1e-3) / 1e9, 1)}
+        del h, out
+        ctx.release_workspaces()
+        torch.cuda.empty_cache()
+    return res
+
+
 def variants_measure(api, wl, torch, p, hd, ctx, base_ms):
     """The NEXT-row options on the same workload: nearest 8x upsampling fused
     into pass A (a 4096^2 design on the 32768^2 grid), band-limited ASM, and
@@ -400,8 +422,10 @@ def main():
         "psf_sum": sumv,
     }
     if not args.no_variants and args.workload == "large" and not args.lambdas:
-        log("variants: fused 8x nearest upsampling, band limit, Lanczos-3 kernels")
+        log("variants: fused 8x nearest upsampling, band limit, Lanczos-3 kernels, paper grids")
         line["variants"] = variants_measure(api, wl, torch, p, hd, ctx, dt * 1e3)
+        log("small and mid workloads")
+        line["other_workloads"] = other_workloads_measure(api, wl, torch, ctx)
     if not args.no_cpu_baseline and args.workload == "large":
         log("timing the CPU oracle on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(h, p)

@@ -216,6 +216,20 @@ def other_workloads_measure(api, wl, torch, ctx):
         res[name] = {"n": q["n"], "m": q["m"], "n_lambda": k, "us_per_call": round(ms * 1e3, 1),
                      "value": round(k * float(q["m"]) ** 2 / (ms * 1e-3) / 1e6, 1),
                      "alg_gbs": round(step / (ms * 1e-3) / 1e9, 1)}
+        if name == "small":
+            # the same call captured once into a HIP graph and replayed
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                api.psf(h, prob, out=out, ctx=ctx)
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                api.psf(h, prob, out=out, ctx=ctx)
+            gms = _event_ms(torch, graph.replay, reps)
+            res[name]["us_per_graph_replay"] = round(gms * 1e3, 1)
+            del graph
         del h, out
         ctx.release_workspaces()
         torch.cuda.empty_cache()

@@ -99,3 +99,51 @@ def test_serve_many_small_requests_overlap(api):
         assert torch.equal(ref, outs[3])
     finally:
         srv.close()
+
+
+def test_serve_mixed_problem_kinds(api):
+    """Requests that use the band limit, the fused 8x nearest upsampling and
+    grids that are not powers of two, mixed with plain ones: each result is
+    bitwise the same as the request run alone, and a sample matches the
+    oracle."""
+    from oracle import upsample as ups
+    rng = np.random.default_rng(13)
+    reqs = []
+    for i in range(16):
+        kind = i % 4
+        lams = np.linspace(0.45, 0.65, 1 + i % 3)
+        z = float(rng.uniform(500.0, 4000.0))
+        if kind == 0:
+            prob = api.Problem(512, 1024, 1.0, z, lams, wl.cauchy_index(lams), bandlimit=True)
+            h = wl.uniform_heights(512, seed=300 + i)
+        elif kind == 1:
+            prob = api.Problem(512, 1024, 0.5, z, lams, wl.cauchy_index(lams), upsample=8)
+            h = wl.uniform_heights(64, seed=300 + i)
+        elif kind == 2:
+            prob = api.Problem(360, 720, 1.0, z, lams, wl.cauchy_index(lams))
+            h = wl.uniform_heights(360, seed=300 + i)
+        else:
+            prob = api.Problem(1500, 3600, 0.5, z, lams, wl.cauchy_index(lams), out_mode="full")
+            h = wl.uniform_heights(1500, seed=300 + i)
+        reqs.append((prob, torch.from_numpy(h).cuda(), h))
+    alone = [api.psf(hd, prob).clone() for prob, hd, _ in reqs]
+    torch.cuda.synchronize()
+    big = max(api.workspace_size(p) for p, _, _ in reqs)
+    srv = api.Server(3 * big, max_slots=4)
+    try:
+        outs = [torch.full(p.out_shape, float("nan"), device="cuda") for p, _, _ in reqs]
+        torch.cuda.synchronize()
+        tickets = [srv.submit(p, hd, o) for (p, hd, _), o in zip(reqs, outs)]
+        for t in tickets:
+            srv.wait(t, 60.0)
+        assert srv.stats()["failed"] == 0
+        for i, (a, b) in enumerate(zip(alone, outs)):
+            assert torch.equal(a, b), f"request {i} differs between alone and mix"
+    finally:
+        srv.close()
+    for i in range(4):
+        prob, _, h = reqs[i]
+        hf = ups.upsample(h, 8, "nearest") if prob.upsample > 1 else h
+        want = oracle.psf(hf, prob.dx, prob.z, prob.m, prob.lambdas, prob.n_index,
+                          out_mode=prob.out_mode, bandlimit=prob.bandlimit)
+        assert np.linalg.norm(alone[i].cpu().numpy() - want) / np.linalg.norm(want) < 2e-5

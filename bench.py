@@ -305,8 +305,8 @@ def variants_measure(api, wl, torch, p, hd, ctx, base_ms):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="large", choices=["large", "mid", "small"])
     ap.add_argument("--lambdas", type=int, default=0,
@@ -362,12 +362,16 @@ def main():
         log(f"warmup step {i + 1}/{args.warmup} done")
 
     ctx.profile_enable(True)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    marks[0].record()
     for i in range(args.steps):
         api.psf(hd, prob, out=psf, ctx=ctx)
+        marks[i + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    step_ms = sorted(marks[i].elapsed_time(marks[i + 1]) for i in range(args.steps))
     prof = ctx.profile_read()
     ctx.profile_enable(False)
     log(f"timed {args.steps} steps in {t1 - t0:.3f} s")
@@ -403,6 +407,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(dt * 1e3, 3),
+        "ms_per_step_median": round(step_ms[len(step_ms) // 2], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

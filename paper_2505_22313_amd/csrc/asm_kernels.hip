@@ -630,19 +630,18 @@ DEV AxisFreq axis_freq(int k, int m, const KParams &p) {
 // in-band s is unchanged).
 DEV double a2_eff(AxisFreq f) { return f.inband ? f.a2 : 2.0; }
 
-// H(ky, kx) / M^2 (conjugated when p.adjoint) from the two axes' a2_eff: zero
-// unless s = a2y + a2x < 1; else exp(i 2 pi (z/lambda) sqrt(1 - s)) with the
-// argument formed and reduced mod one turn in FP64.  Branch-free: cut bins
-// evaluate a dummy argument and are scaled by zero.
+// H(ky, kx) from the two axes' a2_eff: zero unless s = a2y + a2x < 1; else
+// exp(i 2 pi zl sqrt(1 - s)) with the argument formed and reduced mod one
+// turn in FP64.  zl = z / lambda, negated for the adjoint (conj(H) is H at
+// -z).  The inverse DFT's 1/M^2 is left to the last pass's output constants.
+// Branch-free: cut bins evaluate a harmless dummy root (1 - s is floored at
+// 2^-60, below any propagating 1 - s >= 2^-53) and are replaced by zero.
 DEV float2 transfer(double a2y, double a2x, const KParams &p) {
 #pragma clang fp contract(off)
   const double s = a2y + a2x;
-  const bool prop = s < 1.0;
-  const double t = p.zl * sqrt_unit(prop ? 1.0 - s : 1.0);
+  const double t = p.zl * sqrt_unit(fmax(1.0 - s, 0x1p-60));
   const float2 w = cis_turns((float)(t - rint(t)));
-  const float re = prop ? p.inv_m2 : 0.f;
-  const float im = prop ? (p.adjoint ? -p.inv_m2 : p.inv_m2) : 0.f;
-  return make_float2(w.x * re, w.y * im);
+  return s < 1.0 ? w : make_float2(0.f, 0.f);
 }
 
 // Element at a 32-bit byte offset from a block-uniform base: the offset is
@@ -1102,17 +1101,19 @@ DOP_KERNEL(Plan<PID>::TA) void k_pass_a_inv(KParams p) {
           const long long idx = out_index(y, xb0, j + t * LRL, b);
           if (idx < 0) continue;
           const float2 w = u[i][t];
+          // w is M^2 U: the inverse DFT's 1/M^2 is applied here
           if constexpr (OUTM == OUT_PSF) {
-            p.psf[idx] = acc[i][t] + p.wk * (w.x * w.x + w.y * w.y);
-            if (p.saved_out) p.saved_out[idx] = w;
+            p.psf[idx] = acc[i][t] + p.wk_m4 * (w.x * w.x + w.y * w.y);
+            if (p.saved_out) p.saved_out[idx] = cscale(w, p.inv_m2);
           } else if constexpr (OUTM == OUT_FIELD) {
-            p.u_out[idx] = w;
+            p.u_out[idx] = cscale(w, p.inv_m2);
           } else {
             const int x = BX * (j + t * LRL) + xb0 + b;  // crop only: x < n here
             float2 e = doe_phase(p.h[(size_t)(y >> p.up_log2) * p.nh + (x >> p.up_log2)],
                                  p.phase_turns);
             if (p.amp) e = cscale(e, p.amp[idx]);
-            p.grad_h[idx] = acc[i][t] + p.ck * (w.y * e.x - w.x * e.y);  // c_k Im(g_E conj(E))
+            // c_k Im(g_E conj(E)), g_E = w / M^2
+            p.grad_h[idx] = acc[i][t] + p.ck_m2 * (w.y * e.x - w.x * e.y);
           }
         }
       }

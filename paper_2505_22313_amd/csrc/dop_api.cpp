@@ -145,10 +145,11 @@ void fill_common(KParams &kp, const dop_context *ctx, const dop_problem *prob, i
                                           : HUGE_VAL;
   kp.phase_turns = (prob->n_index[k] - 1.0) / lam;
   const float w = prob->weight ? prob->weight[k] : 1.0f;
-  kp.wk = w;
+  const double m2 = (double)prob->m * (double)prob->m;
+  kp.wk_m4 = (float)((double)w / (m2 * m2));
   kp.two_wk = 2.0f * w;
-  kp.ck = (float)(2.0 * M_PI * (prob->n_index[k] - 1.0) / lam);
-  kp.inv_m2 = (float)(1.0 / ((double)prob->m * (double)prob->m));
+  kp.ck_m2 = (float)(2.0 * M_PI * (prob->n_index[k] - 1.0) / lam / m2);
+  kp.inv_m2 = (float)(1.0 / m2);
 }
 
 dop_status launch(const dop_context *cctx, const KParams &kp, hipStream_t stream) {
@@ -438,6 +439,7 @@ dop_status dop_psf_backward(dop_context *ctx, const dop_problem *prob, const flo
     kp.nrows_out = prob->n;
     kp.first = (k == 0);
     kp.adjoint = 1;
+    kp.zl = -kp.zl;  // conj(H) = H at -z (the band limit depends on |z| only)
     kp.h = h;
     kp.amp = amp;
     kp.gpsf = grad_psf;

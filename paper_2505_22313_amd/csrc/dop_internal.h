@@ -42,7 +42,7 @@ struct KParams {
   int in_mode, out_mode;
   int full;              // 1: output the whole M x M plane (centred)
   int first;             // 1: overwrite the accumulator, 0: add to it
-  int adjoint;           // 1: multiply by conj(H)
+  int adjoint;           // 1: adjoint pass (H conjugated through zl < 0)
   const float *h;        // heights (IN_PHASE, OUT_GRADH): row y, column x of
                          // the N x N map is h[(y >> up_log2) * nh + (x >> up_log2)]
   int up_log2;           // log2 of the nearest-neighbour upsampling factor
@@ -56,14 +56,16 @@ struct KParams {
   float2 *saved_out;     // optional N x N copy of U_k (OUT_PSF, crop)
   float *grad_h;         // OUT_GRADH destination
   double phase_turns;    // (n_k - 1) / lambda_k  (turns of phase per unit h)
-  double zl;             // z / lambda_k          (turns at normal incidence)
+  double zl;             // z / lambda_k (turns at normal incidence); -z / lambda_k
+                         // for the adjoint, whose transfer function is conj(H)
   double lam;            // lambda_k
   double inv_mdx;        // 1 / (M dx)
   double flim;           // band limit on |fx| and |fy| (infinity: none)
-  float wk;              // PSF weight w_k
+  float wk_m4;           // w_k / M^4: PSF weight times the squared 1/M^2 of the
+                         // inverse DFT, which the passes leave to the output
   float two_wk;          // 2 w_k
-  float ck;              // 2 pi (n_k - 1) / lambda_k
-  float inv_m2;          // 1 / M^2 (inverse-FFT normalisation)
+  float ck_m2;           // 2 pi (n_k - 1) / lambda_k / M^2
+  float inv_m2;          // 1 / M^2 (inverse-DFT normalisation of output fields)
 };
 
 constexpr int kNumPasses = 5;

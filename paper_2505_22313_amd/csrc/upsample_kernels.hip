@@ -35,21 +35,53 @@ DEV double lanczos3(double x) {
   return 3.0 * sinpi(x) * sinpi(x / 3.0) / (M_PI * M_PI * x * x);
 }
 
+// Fine sample j = q s + r sits at coarse coordinate u = q + f_r with
+// f_r = (r + 0.5)/s - 0.5 in (-1/2, 1/2), so its first tap i0 = floor(u) - 2
+// = q + shift_r and its offsets u - i depend on the residue r only.  A block
+// tabulates, per residue, the raw kernel values L(u - i0 - t) (FP64) and the
+// normalised weights of an interior sample; a sample whose taps leave
+// [0, nc) renormalises over the taps inside.
+struct TapTable {
+  double raw[kUpMaxS][6];
+  float wint[kUpMaxS][6];
+  int shift[kUpMaxS];
+};
+
+DEV void tap_table_fill(TapTable &tt, int s) {
+  for (int r = threadIdx.x; r < s; r += blockDim.x) {
+    const double f = ((double)r + 0.5) / (double)s - 0.5;
+    const int fl = f < 0.0 ? -1 : 0;
+    double sum = 0.0;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      tt.raw[r][t] = lanczos3(f - (double)(fl - 2 + t));
+      sum += tt.raw[r][t];
+    }
+#pragma unroll
+    for (int t = 0; t < 6; ++t) tt.wint[r][t] = (float)(tt.raw[r][t] / sum);
+    tt.shift[r] = fl - 2;
+  }
+}
+
 // Taps of fine sample j: returns i0 and writes the six normalised weights of
 // coarse samples i0 .. i0+5 (zero outside [0, nc)).
-DEV int lanczos_taps(int j, int s, int nc, float *w) {
-  const double u = ((double)j + 0.5) / (double)s - 0.5;
-  const int i0 = (int)floor(u) - 2;
-  double v[6];
-  double sum = 0.0;
+DEV int lanczos_taps(int j, int s, int nc, const TapTable &tt, float *w) {
+  const int q = j / s, r = j - q * s;
+  const int i0 = q + tt.shift[r];
+  if (i0 >= 0 && i0 + 5 < nc) {
 #pragma unroll
-  for (int t = 0; t < 6; ++t) {
-    const int i = i0 + t;
-    v[t] = (i >= 0 && i < nc) ? lanczos3(u - (double)i) : 0.0;
-    sum += v[t];
+    for (int t = 0; t < 6; ++t) w[t] = tt.wint[r][t];
+  } else {
+    double v[6];
+    double sum = 0.0;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      v[t] = (i0 + t >= 0 && i0 + t < nc) ? tt.raw[r][t] : 0.0;
+      sum += v[t];
+    }
+#pragma unroll
+    for (int t = 0; t < 6; ++t) w[t] = (float)(v[t] / sum);
   }
-#pragma unroll
-  for (int t = 0; t < 6; ++t) w[t] = (float)(v[t] / sum);
   return i0;
 }
 
@@ -98,15 +130,18 @@ __global__ __launch_bounds__(256) void k_up_lanczos(int nc, int s, const float *
   __shared__ int rs[kUpTile], cs[kUpTile];
   __shared__ float patch[kUpPatch][kUpPatch + 1];
   __shared__ float vert[kUpTile][kUpPatch + 1];
+  __shared__ TapTable tt;
   const int fy0 = blockIdx.y * kUpTile, fx0 = blockIdx.x * kUpTile;
   const int tid = threadIdx.x;
+  tap_table_fill(tt, s);
+  __syncthreads();
   // taps of every row and column of the tile (clamped to the grid: rows past
   // the edge repeat the last one and are not written)
   if (tid < kUpTile) {
-    rs[tid] = lanczos_taps(min(fy0 + tid, nf - 1), s, nc, rw[tid]);
+    rs[tid] = lanczos_taps(min(fy0 + tid, nf - 1), s, nc, tt, rw[tid]);
   } else if (tid < 2 * kUpTile) {
     const int c = tid - kUpTile;
-    cs[c] = lanczos_taps(min(fx0 + c, nf - 1), s, nc, cw[c]);
+    cs[c] = lanczos_taps(min(fx0 + c, nf - 1), s, nc, tt, cw[c]);
   }
   __syncthreads();
   const int cy0 = rs[0], cx0 = cs[0];
@@ -145,42 +180,64 @@ __global__ __launch_bounds__(256) void k_up_lanczos(int nc, int s, const float *
 // Lanczos-3, adjoint: one 16 x 16 coarse tile per block.  Coarse sample i is
 // a tap of fine sample j only if floor(u_j) is in [i-3, i+2], i.e. j in
 // [s(i-3) - 1, s(i+3) + s]; a tile therefore gathers from at most
-// s (16 + 7) + 2 <= 370 fine rows and as many columns.  Fine rows are staged
-// through LDS 16 at a time and reduced along x into hsum[row][coarse col];
-// the reduction along y follows.
+// s (16 + 6) + 2 fine rows and as many columns (SPAN for s <= SMAX).  Fine
+// rows are staged through LDS 16 at a time, the next chunk loaded into
+// registers while the current one is reduced along x into
+// hsum[row][coarse col]; the reduction along y follows.
 // ---------------------------------------------------------------------------
 constexpr int kAdjTile = 16;
-constexpr int kAdjSpan = kUpMaxS * (kAdjTile + 7) + 2;
 constexpr int kAdjChunk = 16;
+constexpr int kAdjThreads = 256;
 
 DEV int fine_lo(int i, int s) { return s * (i - 3) - 1; }
 DEV int fine_hi(int i, int s) { return s * (i + 3) + s; }
 
-__global__ __launch_bounds__(256) void k_up_lanczos_adj(int nc, int s, const float *__restrict__ g,
-                                                        float *__restrict__ out) {
+template <int SMAX>
+__global__ __launch_bounds__(kAdjThreads) void k_up_lanczos_adj(int nc, int s,
+                                                                const float *__restrict__ g,
+                                                                float *__restrict__ out) {
+  constexpr int SPAN = SMAX * (kAdjTile + 6) + 2;
+  constexpr int PF = (kAdjChunk * SPAN + kAdjThreads - 1) / kAdjThreads;
   const int nf = nc * s;
-  __shared__ float rw[kAdjSpan][6], cw[kAdjSpan][6];
-  __shared__ int rs[kAdjSpan], cs[kAdjSpan];
-  __shared__ float hsum[kAdjSpan][kAdjTile + 1];
-  __shared__ float chunk[kAdjChunk][kAdjSpan + 1];
+  __shared__ TapTable tt;
+  __shared__ float rw[SPAN][6], cw[SPAN][6];
+  __shared__ int rs[SPAN], cs[SPAN];
+  __shared__ float hsum[SPAN][kAdjTile + 1];
+  __shared__ float chunk[kAdjChunk][SPAN + 1];
   const int i0 = blockIdx.y * kAdjTile, k0 = blockIdx.x * kAdjTile;
   const int tid = threadIdx.x;
   const int jlo = max(0, fine_lo(i0, s)), jhi = min(nf - 1, fine_hi(i0 + kAdjTile - 1, s));
   const int llo = max(0, fine_lo(k0, s)), lhi = min(nf - 1, fine_hi(k0 + kAdjTile - 1, s));
   const int nj = jhi - jlo + 1, nl = lhi - llo + 1;
-  for (int e = tid; e < nj; e += blockDim.x) rs[e] = lanczos_taps(jlo + e, s, nc, rw[e]);
-  for (int e = tid; e < nl; e += blockDim.x) cs[e] = lanczos_taps(llo + e, s, nc, cw[e]);
+  tap_table_fill(tt, s);
   __syncthreads();
+  for (int e = tid; e < nj; e += kAdjThreads) rs[e] = lanczos_taps(jlo + e, s, nc, tt, rw[e]);
+  for (int e = tid; e < nl; e += kAdjThreads) cs[e] = lanczos_taps(llo + e, s, nc, tt, cw[e]);
+  float nxt[PF];
+  auto load_chunk = [&](int c0) {
+    const int rows = min(kAdjChunk, nj - c0);
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int e = tid + q * kAdjThreads;
+      const int r = e / nl, c = e - (e / nl) * nl;
+      nxt[q] = r < rows ? g[(size_t)(jlo + c0 + r) * nf + llo + c] : 0.f;
+    }
+  };
   const int kk = tid % kAdjTile;  // coarse column of this thread
   const int k = k0 + kk;
   const int clo = max(0, fine_lo(k, s) - llo), chi = min(nl - 1, fine_hi(k, s) - llo);
+  load_chunk(0);
   for (int c0 = 0; c0 < nj; c0 += kAdjChunk) {
     const int rows = min(kAdjChunk, nj - c0);
-    for (int e = tid; e < rows * nl; e += blockDim.x) {
+    __syncthreads();  // the previous chunk has been consumed
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int e = tid + q * kAdjThreads;
       const int r = e / nl, c = e - (e / nl) * nl;
-      chunk[r][c] = g[(size_t)(jlo + c0 + r) * nf + llo + c];
+      if (r < rows) chunk[r][c] = nxt[q];
     }
     __syncthreads();
+    if (c0 + kAdjChunk < nj) load_chunk(c0 + kAdjChunk);
     const int r = tid / kAdjTile;
     if (r < rows) {
       float a = 0.f;
@@ -190,8 +247,8 @@ __global__ __launch_bounds__(256) void k_up_lanczos_adj(int nc, int s, const flo
       }
       hsum[c0 + r][kk] = a;
     }
-    __syncthreads();
   }
+  __syncthreads();
   const int i = i0 + tid / kAdjTile;
   if (i < nc && k < nc) {
     const int rlo = max(0, fine_lo(i, s) - jlo), rhi = min(nj - 1, fine_hi(i, s) - jlo);
@@ -229,8 +286,12 @@ hipError_t launch_upsample_adjoint(int kind, int nc, int s, const float *grad_fi
                        grad_coarse);
   } else {
     const dim3 grid(cdiv(nc, kAdjTile), cdiv(nc, kAdjTile));
-    hipLaunchKernelGGL(k_up_lanczos_adj, grid, dim3(256), 0, stream, nc, s, grad_fine,
-                       grad_coarse);
+    if (s <= 8)
+      hipLaunchKernelGGL(k_up_lanczos_adj<8>, grid, dim3(kAdjThreads), 0, stream, nc, s, grad_fine,
+                         grad_coarse);
+    else
+      hipLaunchKernelGGL(k_up_lanczos_adj<kUpMaxS>, grid, dim3(kAdjThreads), 0, stream, nc, s,
+                         grad_fine, grad_coarse);
   }
   return hipGetLastError();
 }

@@ -468,7 +468,7 @@ __host__ __device__ constexpr Np2Plan np2_plan(int i) {
          : i == 2 ? Np2Plan{1440, 45, 32, 45, 32}
          : i == 3 ? Np2Plan{3072, 48, 64, 48, 64}
          : i == 4 ? Np2Plan{3600, 225, 16, 15, 240}
-         : i == 5 ? Np2Plan{28800, 450, 64, 60, 480}    // 2^7 3^2 5^2
+         : i == 5 ? Np2Plan{28800, 450, 64, 120, 240}   // 2^7 3^2 5^2
          : i == 6 ? Np2Plan{40000, 625, 64, 100, 400}   // 2^6 5^4
                   : Np2Plan{0, 0, 0, 0, 0};
 }

@@ -63,3 +63,21 @@ def test_design_adam_200_steps(setup):
     print(f"  loss {losses[0]:.4g} -> {losses[-1]:.4g}, {dt * 1e3:.1f} ms/step", flush=True)
     assert all(np.isfinite(losses))
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_design_on_coarse_upsampled_grid(setup):
+    """Design on a coarse grid simulated 8x finer (the paper's conventional
+    design with nearest upsampling): Adam on the 128^2 design lowers the
+    loss, and the design keeps its coarse shape."""
+    api = setup[0]
+    from paper_2505_22313_amd.design import design_loop
+    nc, s, m = 128, 8, 2048
+    n = nc * s
+    lams = np.array([0.5206])
+    prob = api.Problem(n, m, 0.25, 2000.0, lams, wl.cauchy_index(lams), upsample=s)
+    h0 = torch.from_numpy(wl.uniform_heights(nc, seed=5)).cuda()
+    target = torch.from_numpy(wl.gaussian_target(n, 4.0, total=float(n) * n)).cuda()
+    h, losses, _ = design_loop(h0, prob, target, steps=60, lr=2e-2)
+    assert tuple(h.shape) == (nc, nc)
+    assert all(np.isfinite(losses))
+    assert losses[-1] < 0.7 * losses[0]

@@ -89,10 +89,10 @@ def test_lanczos_large_sampled_rows(api):
 
 
 def test_fused_nearest_psf_and_backward(api):
-    """8x nearest upsampling inside pass A: the PSF of a 64^2 design equals
-    the oracle's PSF of its 512^2 upsampled map, and bitwise the library's
-    own PSF of the separately upsampled map; the coarse gradient is the
-    oracle gradient summed over 8 x 8 blocks."""
+    """8x nearest upsampling inside pass A, with a fine-grid aperture: the
+    PSF of a 64^2 design equals the oracle's PSF of its 512^2 upsampled map,
+    and bitwise the library's own PSF of the separately upsampled map; the
+    coarse gradient is the oracle gradient summed over 8 x 8 blocks."""
     nc, s, m, dx, z = 64, 8, 1024, 0.25, 400.0
     n = nc * s
     lams = np.array([0.45, 0.55, 0.65])
@@ -100,20 +100,23 @@ def test_fused_nearest_psf_and_backward(api):
     rng = np.random.default_rng(62)
     hc = rng.uniform(0.0, 1.2, (nc, nc)).astype(np.float32)
     g = rng.standard_normal((n, n)).astype(np.float32)
+    amp = wl.circular_aperture(n, dx, 50.0)
+    ad = dev(amp)
     hf = ups.upsample(hc, s, "nearest")
     pu = api.Problem(n, m, dx, z, lams, nidx, upsample=s)
     pf = api.Problem(n, m, dx, z, lams, nidx)
-    got, saved = api.psf(dev(hc), pu, save_fields=True)
-    want = oracle.psf(hf, dx, z, m, lams, nidx)
+    got, saved = api.psf(dev(hc), pu, amp=ad, save_fields=True)
+    want = oracle.psf(hf, dx, z, m, lams, nidx, amp=amp)
     assert rel(got.cpu().numpy(), want) < INTENSITY_TOL
     hf_dev = api.upsample(dev(hc), s, "nearest")
-    ref, saved_ref = api.psf(hf_dev, pf, save_fields=True)
+    ref, saved_ref = api.psf(hf_dev, pf, amp=ad, save_fields=True)
     assert torch.equal(got, ref) and torch.equal(saved, saved_ref)
-    gc = api.psf_backward(dev(hc), pu, saved, dev(g))
+    gc = api.psf_backward(dev(hc), pu, saved, dev(g), amp=ad)
     assert tuple(gc.shape) == (nc, nc)
-    want_g = ups.upsample_adjoint(oracle.psf_backward(hf, dx, z, m, lams, nidx, g), s, "nearest")
+    want_g = ups.upsample_adjoint(oracle.psf_backward(hf, dx, z, m, lams, nidx, g, amp=amp), s,
+                                  "nearest")
     assert rel(gc.cpu().numpy(), want_g) < GRAD_TOL
-    gf = api.psf_backward(hf_dev, pf, saved_ref, dev(g))
+    gf = api.psf_backward(hf_dev, pf, saved_ref, dev(g), amp=ad)
     assert torch.equal(gc, api.upsample_adjoint(gf, s, "nearest"))
 
 

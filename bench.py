@@ -473,6 +473,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            "traffic_gbs": None if traffic is None else round(traffic / (dp["avg_ms"] * 1e-3) / 1e9, 1),
             "copy_ceiling_gbs": round(copy_gbs, 1),
             "frac_of_copy": round(achieved / copy_gbs, 4),
         },

@@ -283,7 +283,8 @@ dop_status dop_serve_latency(dop_server *srv, uint64_t ticket, double *ms);
 dop_status dop_serve_stats_get(dop_server *srv, dop_serve_stats *out);
 
 /* Stop admitting, cancel queued requests (DOP_ERR_SHUTDOWN), wait for
- * running ones, free everything. */
+ * running ones, free everything.  No other call on `srv` may be in progress
+ * or follow (tickets die with the server). */
 dop_status dop_serve_destroy(dop_server *srv);
 
 /*

@@ -298,6 +298,9 @@ dop_status dop_serve_submit(dop_server *srv, const dop_problem *prob, const floa
   dop_status s = validate_problem(prob);
   if (s != DOP_OK) return s;
   if (!h || !psf) return fail(DOP_ERR_INVALID_ARG, "h / psf must not be NULL");
+  auto misaligned = [](const void *q) { return reinterpret_cast<uintptr_t>(q) % 4 != 0; };
+  if (misaligned(h) || misaligned(psf) || (amp && misaligned(amp)))
+    return fail(DOP_ERR_INVALID_ARG, "float arrays must be 4-byte aligned");
   auto r = std::make_unique<Request>();
   r->prob = *prob;
   r->lam.assign(prob->lambda, prob->lambda + prob->n_lambda);

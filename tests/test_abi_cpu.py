@@ -209,9 +209,9 @@ def test_serve_fifo_head_of_line():
     unit = ws(1024)                    # one 1024^2 workspace
     srv = api.Server(ws(2048), max_slots=4, mock_us_per_mpix=3000.0)
     try:
-        a = srv.submit(req(1024, 4), 1, 2)   # 1 unit, ~12.6 ms
-        big = srv.submit(req(2048), 1, 2)    # the whole arena: must wait for a
-        c = srv.submit(req(1024), 1, 2)      # 1 unit: fits now, but queued behind big
+        a = srv.submit(req(1024, 4), 256, 512)   # 1 unit, ~12.6 ms
+        big = srv.submit(req(2048), 256, 512)    # the whole arena: must wait for a
+        c = srv.submit(req(1024), 256, 512)      # 1 unit: fits now, but queued behind big
         for t in (a, big, c):
             srv.wait(t, 10.0)
         la, lb, lc = srv.latency_ms(a), srv.latency_ms(big), srv.latency_ms(c)
@@ -223,7 +223,7 @@ def test_serve_fifo_head_of_line():
 
 def test_serve_shutdown_cancels_queue_and_unknown_ticket():
     srv = api.Server(ws(1024), max_slots=1, mock_us_per_mpix=5000.0)
-    tickets = [srv.submit(req(1024), 1, 2) for _ in range(4)]
+    tickets = [srv.submit(req(1024), 256, 512) for _ in range(4)]
     assert lib().dop_serve_poll(srv.handle, 999999) == L.DOP_ERR_NOT_FOUND
     st = lib().dop_serve_wait(srv.handle, tickets[-1], 0.001)
     assert st == L.DOP_ERR_TIMEOUT
@@ -232,8 +232,8 @@ def test_serve_shutdown_cancels_queue_and_unknown_ticket():
 
 def test_serve_cancelled_status_visible_before_destroy():
     srv = api.Server(ws(1024), max_slots=1, mock_us_per_mpix=5000.0)
-    t1 = srv.submit(req(1024), 1, 2)
-    t2 = srv.submit(req(1024), 1, 2)
+    t1 = srv.submit(req(1024), 256, 512)
+    t2 = srv.submit(req(1024), 256, 512)
     # destroy in a helper thread would free the server; instead check that the
     # queued request is reported as not ready, then finish normally
     assert srv.poll(t2) == L.DOP_NOT_READY
@@ -251,6 +251,19 @@ def test_serve_rejects_bad_create_args():
                                        ctypes.byref(h)) == L.DOP_ERR_INVALID_ARG
     assert lib().dop_serve_create_mock(ctypes.c_void_p(256), 1 << 20, 2, -1.0,
                                        ctypes.byref(h)) == L.DOP_ERR_INVALID_ARG
+
+
+def test_serve_submit_rejects_misaligned_buffers():
+    srv = api.Server(1 << 30, max_slots=2, mock_us_per_mpix=0.0)
+    try:
+        for h, out in ((258, 512), (256, 514)):
+            with pytest.raises(L.DopError) as e:
+                srv.submit(good(), h, out)
+            assert e.value.status == L.DOP_ERR_INVALID_ARG
+        t = srv.submit(good(), 256, 512)
+        srv.wait(t, 10.0)
+    finally:
+        srv.close()
 
 
 def test_upsampled_problem_workspace():

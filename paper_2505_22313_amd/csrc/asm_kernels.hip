@@ -165,6 +165,77 @@ struct Dft<5, INV> {
   }
 };
 
+// cos(2 pi q / R) and sin(2 pi q / R), q < R, for the composite radices
+// (values of the unit circle rounded to float).
+template <int R>
+struct UnitRoots;
+template <>
+struct UnitRoots<9> {
+  static constexpr float c[9] = {
+      1.000000000e+00f, 7.660444431e-01f, 1.736481777e-01f, -5.000000000e-01f,
+      -9.396926208e-01f, -9.396926208e-01f, -5.000000000e-01f, 1.736481777e-01f,
+      7.660444431e-01f};
+  static constexpr float s[9] = {
+      0.000000000e+00f, 6.427876097e-01f, 9.848077530e-01f, 8.660254038e-01f,
+      3.420201433e-01f, -3.420201433e-01f, -8.660254038e-01f, -9.848077530e-01f,
+      -6.427876097e-01f};
+};
+template <>
+struct UnitRoots<15> {
+  static constexpr float c[15] = {
+      1.000000000e+00f, 9.135454576e-01f, 6.691306064e-01f, 3.090169944e-01f,
+      -1.045284633e-01f, -5.000000000e-01f, -8.090169944e-01f, -9.781476007e-01f,
+      -9.781476007e-01f, -8.090169944e-01f, -5.000000000e-01f, -1.045284633e-01f,
+      3.090169944e-01f, 6.691306064e-01f, 9.135454576e-01f};
+  static constexpr float s[15] = {
+      0.000000000e+00f, 4.067366431e-01f, 7.431448255e-01f, 9.510565163e-01f,
+      9.945218954e-01f, 8.660254038e-01f, 5.877852523e-01f, 2.079116908e-01f,
+      -2.079116908e-01f, -5.877852523e-01f, -8.660254038e-01f, -9.945218954e-01f,
+      -9.510565163e-01f, -7.431448255e-01f, -4.067366431e-01f};
+};
+
+// R = R1 * R2 from two in-register DFTs (four-step split n = n1 R2 + n2,
+// k = k1 + R1 k2, twiddles omega_R^(n2 k1) from UnitRoots<R>).
+template <int R1, int R2, bool INV>
+struct DftComposite {
+  static constexpr int R = R1 * R2;
+  DEV static void run(float2 *a) {
+    float2 t[R];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+      float2 b[R1];
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) b[n1] = a[n1 * R2 + n2];
+      Dft<R1, INV>::run(b);
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) {
+        const int q = (n2 * k1) % R;
+        if (q == 0) {
+          t[k1 * R2 + n2] = b[k1];
+        } else {
+          const float c = UnitRoots<R>::c[q];
+          const float sn = INV ? UnitRoots<R>::s[q] : -UnitRoots<R>::s[q];
+          t[k1 * R2 + n2] = make_float2(b[k1].x * c - b[k1].y * sn, b[k1].x * sn + b[k1].y * c);
+        }
+      }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+      float2 c[R2];
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) c[n2] = t[k1 * R2 + n2];
+      Dft<R2, INV>::run(c);
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) a[k1 + R1 * k2] = c[k2];
+    }
+  }
+};
+
+template <bool INV>
+struct Dft<9, INV> : DftComposite<3, 3, INV> {};
+template <bool INV>
+struct Dft<15, INV> : DftComposite<3, 5, INV> {};
+
 // R = 4 * R2 (R = 8, 16): four-step split n = n1*R2 + n2, k = k1 + 4*k2.
 template <int R, bool INV>
 struct Dft {
@@ -197,11 +268,15 @@ struct Dft {
 // ---------------------------------------------------------------------------
 // Stockham stage plan for an L-point DFT, L = 2^a 3^b 5^c <= 1024: the
 // power-of-two factor in radix 16/8/4 stages (as for a power-of-two L), then
-// one radix-5 stage per factor 5, then one radix-3 stage per factor 3.
+// the odd factor: a radix-15 stage per (3, 5) pair, radix 9 per pair of the
+// remaining threes, radix 5 per remaining five, a last radix 3.  (Radix 25
+// would save more stages, but 25 points per item plus the prefetched inputs
+// overflow the 128 registers a thread has at this occupancy.)
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 __host__ __device__ constexpr bool is_pow2c(int v) { return v > 0 && (v & (v - 1)) == 0; }
 __host__ __device__ constexpr int pow2_part(int v) { return v % 2 ? 1 : 2 * pow2_part(v / 2); }
+__host__ __device__ constexpr int cmin_(int a, int b) { return a < b ? a : b; }
 __host__ __device__ constexpr int count_factor(int v, int f) {
   return v % f ? 0 : 1 + count_factor(v / f, f);
 }
@@ -220,16 +295,29 @@ __host__ __device__ constexpr int fwd_radix_p2(int L, int s) {
        : (s == 0 ? 16 : 8);  // 1024
 }
 
+__host__ __device__ constexpr int n15(int L) {
+  return cmin_(count_factor(L, 3), count_factor(L, 5));
+}
+__host__ __device__ constexpr int n9(int L) { return (count_factor(L, 3) - n15(L)) / 2; }
+__host__ __device__ constexpr int n5(int L) { return count_factor(L, 5) - n15(L); }
+__host__ __device__ constexpr int n3(int L) { return (count_factor(L, 3) - n15(L)) % 2; }
+
 __host__ __device__ constexpr int num_stages(int L) {
-  return L <= 1 ? 1
-                : num_stages_p2(pow2_part(L)) + count_factor(L, 5) + count_factor(L, 3);
+  return L <= 1 ? 1 : num_stages_p2(pow2_part(L)) + n15(L) + n9(L) + n5(L) + n3(L);
+}
+
+// radix of odd-factor stage s (s counted from the first odd stage)
+__host__ __device__ constexpr int odd_radix(int L, int s) {
+  return s < n15(L)                     ? 15
+         : s < n15(L) + n9(L)           ? 9
+         : s < n15(L) + n9(L) + n5(L)   ? 5
+                                        : 3;
 }
 
 __host__ __device__ constexpr int fwd_radix(int L, int s) {
   return L <= 1 ? 1
-       : s < num_stages_p2(pow2_part(L))
-           ? fwd_radix_p2(pow2_part(L), s)
-           : (s - num_stages_p2(pow2_part(L)) < count_factor(L, 5) ? 5 : 3);
+       : s < num_stages_p2(pow2_part(L)) ? fwd_radix_p2(pow2_part(L), s)
+                                         : odd_radix(L, s - num_stages_p2(pow2_part(L)));
 }
 
 // REV reverses the radix order (used by the inverse half of the fused middle

@@ -125,36 +125,43 @@ def serve_measure(api, wl, torch, count, rate_hz, pool, slots=4, seed=5):
         lat_seq.append((time.perf_counter() - t0 - ta) * 1e3)
     span_seq = time.perf_counter() - t0
 
-    # continuous batching
+    # continuous batching, under each admission policy
     big = max(api.workspace_size(p) for _, p, _ in reqs)
-    srv = api.Server(slots * big, max_slots=slots)
-    tickets = [None] * len(reqs)
-    t0 = time.perf_counter()
 
-    def submitter():
-        for i, ((ta, prob, h), o) in enumerate(zip(reqs, outs)):
-            now = time.perf_counter() - t0
-            if now < ta:
-                time.sleep(ta - now)
-            tickets[i] = srv.submit(prob, h, o)
+    def served(policy):
+        srv = api.Server(slots * big, max_slots=slots, policy=policy)
+        tickets = [None] * len(reqs)
+        t0 = time.perf_counter()
 
-    th = threading.Thread(target=submitter)
-    th.start()
-    th.join()
-    for t in tickets:
-        srv.wait(t, 600.0)
-    span_srv = time.perf_counter() - t0
-    lat_srv = [srv.latency_ms(t) for t in tickets]
-    peak = srv.stats()["arena_peak"]
-    srv.close()
+        def submitter():
+            for i, ((ta, prob, h), o) in enumerate(zip(reqs, outs)):
+                now = time.perf_counter() - t0
+                if now < ta:
+                    time.sleep(ta - now)
+                tickets[i] = srv.submit(prob, h, o)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join()
+        for t in tickets:
+            srv.wait(t, 600.0)
+        span = time.perf_counter() - t0
+        lat = [srv.latency_ms(t) for t in tickets]
+        peak = srv.stats()["arena_peak"]
+        srv.close()
+        return {"p50_ms": round(_pct(lat, 0.5), 2), "p99_ms": round(_pct(lat, 0.99), 2),
+                "throughput_req_s": round(count / span, 2),
+                "mpix_lambda_s": round(work / span, 1), "arena_peak_gb": round(peak / 1e9, 2)}
+
+    res_fifo = served("fifo")
+    res_size = served("size_aware")
     del outs
     torch.cuda.synchronize()
     return {
         "requests": count, "offered_rate_hz": round(rate_hz, 2), "slots": slots,
         "mpix_lambda": round(work, 1),
-        "served": {"p50_ms": round(_pct(lat_srv, 0.5), 2), "p99_ms": round(_pct(lat_srv, 0.99), 2),
-                   "throughput_req_s": round(count / span_srv, 2),
-                   "mpix_lambda_s": round(work / span_srv, 1), "arena_peak_gb": round(peak / 1e9, 2)},
+        "served": res_fifo,
+        "served_size_aware": res_size,
         "sequential": {"p50_ms": round(_pct(lat_seq, 0.5), 2),
                        "p99_ms": round(_pct(lat_seq, 0.99), 2),
                        "throughput_req_s": round(count / span_seq, 2),

@@ -269,6 +269,22 @@ dop_status dop_serve_submit(dop_server *srv, const dop_problem *prob,
                             const float *h, const float *amp, float *psf,
                             uint64_t *ticket);
 
+/* Admission policies.  Both admit in submission order (the head of the queue
+ * waits until a slot and arena memory are free).
+ *   DOP_SERVE_FIFO (default): the head starts as soon as it fits, beside
+ *     whatever runs.
+ *   DOP_SERVE_SIZE_AWARE: while requests run, the head starts only if its
+ *     work (n_lambda * m^2) is at most share_ratio times the largest running
+ *     request's; otherwise it waits for the GPU to drain.  Large requests
+ *     then run one after another, each sharing the GPU only with small ones,
+ *     which keeps their latency close to running alone while small requests
+ *     still start beside them. */
+enum { DOP_SERVE_FIFO = 0, DOP_SERVE_SIZE_AWARE = 1 };
+
+/* Set the admission policy (applies to requests not yet started).
+ * share_ratio >= 0 is used by DOP_SERVE_SIZE_AWARE. */
+dop_status dop_serve_set_policy(dop_server *srv, int policy, double share_ratio);
+
 /* DOP_OK when done, DOP_NOT_READY while queued/running, or the request's
  * error.  A finished ticket can be polled any number of times. */
 dop_status dop_serve_poll(dop_server *srv, uint64_t ticket);

@@ -30,6 +30,8 @@ DOP_BANDLIMIT = 1
 DOP_UPSAMPLE_NEAREST = 0
 DOP_UPSAMPLE_LANCZOS3 = 1
 DOP_MAX_UPSAMPLE = 16
+DOP_SERVE_FIFO = 0
+DOP_SERVE_SIZE_AWARE = 1
 
 DOP_OUT_CROP = 0
 DOP_OUT_FULL = 1
@@ -101,6 +103,7 @@ _SIGNATURES = {
     "dop_serve_create_mock": (ctypes.c_int, [_VP, ctypes.c_size_t, ctypes.c_int, ctypes.c_double,
                                              ctypes.POINTER(_VP)]),
     "dop_serve_submit": (ctypes.c_int, [_VP, _PROB, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_uint64)]),
+    "dop_serve_set_policy": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_double]),
     "dop_serve_poll": (ctypes.c_int, [_VP, ctypes.c_uint64]),
     "dop_serve_wait": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_double]),
     "dop_serve_latency": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]),

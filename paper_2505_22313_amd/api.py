@@ -308,7 +308,10 @@ class DopUpsample(torch.autograd.Function):
 class Server:
     """Continuous-batching PSF server over a device arena (see dop.h)."""
 
-    def __init__(self, arena_bytes, max_slots=4, ctx=None, mock_us_per_mpix=None):
+    POLICIES = {"fifo": L.DOP_SERVE_FIFO, "size_aware": L.DOP_SERVE_SIZE_AWARE}
+
+    def __init__(self, arena_bytes, max_slots=4, ctx=None, mock_us_per_mpix=None,
+                 policy="fifo", share_ratio=0.25):
         self.mock = mock_us_per_mpix is not None
         h = ctypes.c_void_p()
         if self.mock:
@@ -325,6 +328,12 @@ class Server:
                                          int(max_slots), ctypes.byref(h)), "dop_serve_create")
         self.handle = h
         self._keep = {}
+        self.set_policy(policy, share_ratio)
+
+    def set_policy(self, policy, share_ratio=0.25):
+        """Admission policy: "fifo" or "size_aware" (see dop_serve_set_policy)."""
+        check(lib().dop_serve_set_policy(self.handle, self.POLICIES[policy], float(share_ratio)),
+              "dop_serve_set_policy")
 
     def submit(self, prob, h, out, amp=None):
         """Queue a PSF request; h/amp/out are device tensors (or, for a mock

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -185,10 +186,17 @@ struct dop_server {
   uint64_t next_ticket = 1;
   uint64_t submitted = 0, completed = 0, failed = 0;
   bool stopping = false;
+  int policy = DOP_SERVE_FIFO;
+  double share_ratio = 0.25;
   std::thread sched;
 
   dop_server(char *base, size_t bytes, int n) : arena_base(base), arena(bytes), max_slots(n),
                                                 slots(n, nullptr) {}
+
+  // padded pixels x wavelengths: the request's share of GPU time
+  static double work(const Request &r) {
+    return (double)r.prob.n_lambda * (double)r.prob.m * (double)r.prob.m;
+  }
 
   void finish(Request *r, dop_status st) {
     r->status = st;
@@ -223,6 +231,13 @@ struct dop_server {
         for (int s = 0; s < max_slots; ++s)
           if (!slots[s]) { free_slot = s; break; }
         if (free_slot < 0) break;
+        if (policy == DOP_SERVE_SIZE_AWARE && running > 0) {
+          // the head shares the GPU only if it is small next to what runs
+          double wmax = 0.0;
+          for (Request *q : slots)
+            if (q) wmax = std::max(wmax, work(*q));
+          if (work(*r) > share_ratio * wmax) break;
+        }
         size_t off = 0;
         if (!arena.alloc(r->need, &off)) break;  // FIFO: the head waits for memory
         queue.pop_front();
@@ -327,6 +342,22 @@ dop_status dop_serve_submit(dop_server *srv, const dop_problem *prob, const floa
     srv->queue.push_back(r.get());
     srv->all.emplace(r->ticket, std::move(r));
     ++srv->submitted;
+  }
+  srv->cv_work.notify_one();
+  return DOP_OK;
+}
+
+dop_status dop_serve_set_policy(dop_server *srv, int policy, double share_ratio) {
+  clear_error();
+  if (!srv) return fail(DOP_ERR_INVALID_ARG, "server is NULL");
+  if (policy != DOP_SERVE_FIFO && policy != DOP_SERVE_SIZE_AWARE)
+    return fail(DOP_ERR_INVALID_ARG, "unknown policy %d", policy);
+  if (!(share_ratio >= 0.0) || !std::isfinite(share_ratio))
+    return fail(DOP_ERR_INVALID_ARG, "share_ratio must be finite and >= 0");
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->policy = policy;
+    srv->share_ratio = share_ratio;
   }
   srv->cv_work.notify_one();
   return DOP_OK;

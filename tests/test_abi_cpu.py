@@ -312,3 +312,38 @@ def test_upsample_argument_checks(args, code):
     st = lib().dop_upsample_adjoint(ctx, kind, nc, s, ctypes.c_void_p(b),
                                     ctypes.c_void_p(a) if a else None, None)
     assert st == code, L.last_error()
+
+
+@pytest.mark.parametrize("policy", ["fifo", "size_aware"])
+def test_serve_size_aware_policy(policy):
+    """Mock service time ~ work (n_lambda m^2).  Under the size-aware policy a
+    second large request waits for the first to finish while a small one
+    starts beside it; under FIFO both large ones start at once."""
+    srv = api.Server(1 << 30, max_slots=4, mock_us_per_mpix=1500.0, policy=policy,
+                     share_ratio=0.25)
+    try:
+        big1 = srv.submit(req(2048, 4), 256, 512)    # 16.8 Mpix*lambda: ~25 ms
+        small = srv.submit(req(512), 256, 512)       # 0.26 Mpix*lambda: ~0.4 ms
+        big2 = srv.submit(req(2048, 4), 256, 512)
+        for t in (big1, small, big2):
+            assert srv.wait(t, 10.0) == L.DOP_OK
+        l1, ls, l2 = srv.latency_ms(big1), srv.latency_ms(small), srv.latency_ms(big2)
+        assert ls < 0.5 * l1                          # the small one never waited for big1
+        if policy == "size_aware":
+            assert l2 > 1.8 * l1                      # big2 ran after big1
+        else:
+            assert l2 < 1.5 * l1                      # big2 ran beside big1
+    finally:
+        srv.close()
+
+
+def test_serve_set_policy_validation():
+    srv = api.Server(1 << 20, max_slots=1, mock_us_per_mpix=0.0)
+    try:
+        assert lib().dop_serve_set_policy(srv.handle, 7, 0.25) == L.DOP_ERR_INVALID_ARG
+        assert lib().dop_serve_set_policy(srv.handle, 1, -1.0) == L.DOP_ERR_INVALID_ARG
+        assert lib().dop_serve_set_policy(srv.handle, 1, float("nan")) == L.DOP_ERR_INVALID_ARG
+        assert lib().dop_serve_set_policy(None, 1, 0.25) == L.DOP_ERR_INVALID_ARG
+        assert lib().dop_serve_set_policy(srv.handle, 1, 0.5) == L.DOP_OK
+    finally:
+        srv.close()

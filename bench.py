@@ -345,6 +345,27 @@ def variants_measure(api, wl, torch, p, hd, ctx, base_ms):
         ctx.release_workspaces()
         torch.cuda.empty_cache()
     res["np2_grids"] = grids
+    # the largest grid one GPU holds: 65536^2 DOE padded to 131072^2 (137 GB workspace)
+    ctx.release_workspaces()
+    torch.cuda.empty_cache()
+    n_h, m_h = 65536, 131072
+    lams3 = np.array([0.45, 0.55, 0.65])
+    hh = torch.rand((n_h, n_h), generator=torch.Generator(device="cuda").manual_seed(17),
+                    device="cuda") * 1.2
+    ph = api.Problem(n_h, m_h, p["dx"], p["z"], lams3, wl.cauchy_index(lams3))
+    oh = torch.empty((n_h, n_h), dtype=torch.float32, device="cuda")
+    ctx.profile_enable(True)
+    ms = _event_ms(torch, lambda: api.psf(hh, ph, out=oh, ctx=ctx), 1)
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    pb = pass_bytes(n_h, m_h, k_first=False)
+    res["largest_grid"] = {
+        "n": n_h, "m": m_h, "n_lambda": 3, "workspace_gb": round(api.workspace_size(ph) / 1e9, 1),
+        "ms_per_step": round(ms, 1), "value": round(3 * float(m_h) ** 2 / (ms * 1e-3) / 1e6, 1),
+        "passes_alg_gbs": {k: round(pb[k] / (v[1] / v[0] * 1e-3) / 1e9, 1) for k, v in prof.items()}}
+    del hh, oh
+    ctx.release_workspaces()
+    torch.cuda.empty_cache()
     return res
 
 

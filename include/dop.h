@@ -48,7 +48,7 @@ typedef enum {
   DOP_NOT_READY = 1,            /* serve: ticket still queued or running   */
   DOP_ERR_INVALID_ARG = -1,     /* malformed argument                      */
   DOP_ERR_UNSUPPORTED = -2,     /* valid but not supported (e.g. an M with
-                                   no plan, M > 65536)                      */
+                                   no plan, M > 131072)                     */
   DOP_ERR_WORKSPACE = -3,       /* workspace missing or too small          */
   DOP_ERR_DEVICE = -4,          /* HIP runtime or launch failure           */
   DOP_ERR_BUDGET = -5,          /* serve: request can never fit the arena  */
@@ -83,7 +83,7 @@ enum {
 enum { DOP_OP_PROPAGATE = 0, DOP_OP_PSF = 1, DOP_OP_PSF_BACKWARD = 2 };
 
 /* Limits. */
-#define DOP_MAX_M 65536
+#define DOP_MAX_M 131072
 #define DOP_MIN_M 16
 #define DOP_MAX_LAMBDA 64
 #define DOP_MAX_UPSAMPLE 16
@@ -95,7 +95,8 @@ enum { DOP_OP_PROPAGATE = 0, DOP_OP_PSF = 1, DOP_OP_PSF_BACKWARD = 2 };
 typedef struct {
   int32_t n;             /* DOE grid n x n, 1 <= n <= m                       */
   int32_t m;             /* padded FFT grid m x m: a power of two in
-                            16..65536, or one of the grids 240, 720, 1440,
+                            16..131072 (137 GB of workspace at 131072), or
+                            one of the grids 240, 720, 1440,
                             3072, 3600, 28800 (= 2^7 3^2 5^2) and 40000
                             (= 2^6 5^4, the paper's Table 2 grids)         */
   double dx;             /* sampling pitch (> 0)                              */
@@ -127,7 +128,7 @@ const char *dop_last_error(void);
 
 /*
  * Create a context on HIP device `device`: uploads the twiddle table
- * (exp(-2 pi i j / 65536), generated in FP64 and rounded to c64, 512 KiB).
+ * (exp(-2 pi i j / 131072), generated in FP64 and rounded to c64, 1 MiB).
  * The context owns only that table.  Synchronous.
  */
 dop_status dop_context_create(int device, dop_context **out);

@@ -537,9 +537,12 @@ struct NoStore {
 __host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 __host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 __host__ __device__ constexpr int round64(int v) { return (v + 63) / 64 * 64; }
-__host__ __device__ constexpr int plan_bx(int lm) { return cmin(lm / 2, 6); }
+// M = 2^17 splits both axes 1024 x 128: its B and C tiles hold 16384 points
+// (one 1024-thread block per CU), the only way to keep every digit <= 1024
+// and the pass-C runs 16 columns wide.
+__host__ __device__ constexpr int plan_bx(int lm) { return lm == 17 ? 7 : cmin(lm / 2, 6); }
 __host__ __device__ constexpr int plan_ay(int lm) {
-  return cmin(cmin(lm / 2, 7), 13 - plan_bx(lm));
+  return lm == 17 ? 7 : cmin(cmin(lm / 2, 7), 13 - plan_bx(lm));
 }
 __host__ __device__ constexpr int threads_for(int pts) {
   return round64(cmin(512, cmax(64, pts / 16)));
@@ -581,8 +584,10 @@ struct Plan {
   // (other M: about 8 points per thread, since their mixed-radix stage
   // shapes do not divide evenly among threads and need more registers each)
   static constexpr int TA = round64(cmin(1024, cmax(64, AX * RA / (POW2 ? 16 : 8))));
-  static constexpr int TB = POW2 ? threads_for(BX * AY) : round64(cmin(1024, cmax(64, BX * AY / 8)));
-  static constexpr int TC = POW2 ? threads_for(BY * RC) : round64(cmin(1024, cmax(64, BY * RC / 8)));
+  static constexpr int TB = !POW2 ? round64(cmin(1024, cmax(64, BX * AY / 8)))
+                            : BX * AY > 8192 ? 1024 : threads_for(BX * AY);
+  static constexpr int TC = !POW2 ? round64(cmin(1024, cmax(64, BY * RC / 8)))
+                            : BY * RC > 8192 ? 1024 : threads_for(BY * RC);
   // Twiddles in LDS: omega_M^q = HI[q / S] * LO[q % S] with HI[i] = omega_M^(i S)
   // (= omega_THI^i) and LO[i] = omega_M^i.  Power-of-two M: THI = min(M, 1024),
   // which also serves every inner DFT length.  Other M: THI = AX (S = BX), the
@@ -592,7 +597,7 @@ struct Plan {
   static constexpr int LOGS = ilog2c(S);
   static_assert(AX * BX == M && AY * BY == M, "digit split");
   static_assert(is_pow2c(BX) && BX % RA == 0 && M % RC == 0, "runs");
-  static_assert(AX * RA <= 16384 && BX * AY <= 8192 && BY * RC <= 8192, "tile sizes");
+  static_assert(AX * RA <= 16384 && BX * AY <= 16384 && BY * RC <= 16384, "tile sizes");
   static_assert(AX <= 1024 && BX <= 1024 && AY <= 1024 && BY <= 1024, "digit lengths");
 };
 
@@ -1265,6 +1270,7 @@ hipError_t launch_wavelength(const KParams &p, hipStream_t s, hipEvent_t *ev) {
     case 14: return launch_impl<14>(p, s, ev);
     case 15: return launch_impl<15>(p, s, ev);
     case 16: return launch_impl<16>(p, s, ev);
+    case 17: return launch_impl<17>(p, s, ev);
     case kNp2Base + 0: return launch_impl<kNp2Base + 0>(p, s, ev);
     case kNp2Base + 1: return launch_impl<kNp2Base + 1>(p, s, ev);
     case kNp2Base + 2: return launch_impl<kNp2Base + 2>(p, s, ev);
@@ -1278,7 +1284,7 @@ hipError_t launch_wavelength(const KParams &p, hipStream_t s, hipEvent_t *ev) {
 static_assert(kNumNp2 == 7, "one launch case per grid of np2_plan");
 
 int plan_id(int m) {
-  if (m >= 16 && m <= 65536 && is_pow2c(m)) return ilog2c(m);
+  if (m >= 16 && m <= (1 << 17) && is_pow2c(m)) return ilog2c(m);
   for (int i = 0; i < kNumNp2; ++i)
     if (np2_plan(i).m == m) return kNp2Base + i;
   return -1;
@@ -1311,6 +1317,7 @@ bool plan_info(int plan, PlanInfo *o) {
     case 14: fill_plan<14>(o); return true;
     case 15: fill_plan<15>(o); return true;
     case 16: fill_plan<16>(o); return true;
+    case 17: fill_plan<17>(o); return true;
     case kNp2Base + 0: fill_plan<kNp2Base + 0>(o); return true;
     case kNp2Base + 1: fill_plan<kNp2Base + 1>(o); return true;
     case kNp2Base + 2: fill_plan<kNp2Base + 2>(o); return true;

@@ -9,7 +9,7 @@
 namespace dop {
 
 // Size of the shared twiddle table: W[j] = exp(-2 pi i j / kTwN).
-constexpr int kTwLog = 16;
+constexpr int kTwLog = 17;
 constexpr int kTwN = 1 << kTwLog;
 
 // Row pitch of the M x M workspace, in elements: M + kRowPad.  The pad keeps
@@ -75,7 +75,7 @@ constexpr int kNumPasses = 5;
 // after the last one.
 hipError_t launch_wavelength(const KParams &p, hipStream_t stream, hipEvent_t *ev);
 
-// Plan id of grid size M: log2(M) for a power of two in [16, 65536], a
+// Plan id of grid size M: log2(M) for a power of two in [16, 131072], a
 // larger id for each supported grid that is not a power of two, -1 if M has
 // no plan.
 int plan_id(int m);

@@ -53,7 +53,7 @@ def good(**kw):
 
 
 def test_workspace_size_valid():
-    for m in [16, 1024, 65536, 240, 720, 1440, 3072, 3600, 28800, 40000]:
+    for m in [16, 1024, 65536, 131072, 240, 720, 1440, 3072, 3600, 28800, 40000]:
         st, b = _ws(good(n=m // 2, m=m))
         assert st == L.DOP_OK and b == 8 * m * (m + 16)
     for op in (L.DOP_OP_PROPAGATE, L.DOP_OP_PSF, L.DOP_OP_PSF_BACKWARD):
@@ -64,7 +64,7 @@ def test_workspace_size_valid():
     (dict(m=1000), L.DOP_ERR_UNSUPPORTED),          # not a supported grid
     (dict(m=30000, n=100), L.DOP_ERR_UNSUPPORTED),   # 2^4 3 5^4: no plan
     (dict(m=2 * 28800, n=100), L.DOP_ERR_UNSUPPORTED),
-    (dict(m=131072, n=100), L.DOP_ERR_UNSUPPORTED),  # beyond 65536
+    (dict(m=262144, n=100), L.DOP_ERR_UNSUPPORTED),  # beyond 131072
     (dict(m=8, n=4), L.DOP_ERR_UNSUPPORTED),         # below the minimum
     (dict(n=2048), L.DOP_ERR_INVALID_ARG),           # n > m
     (dict(n=0), L.DOP_ERR_INVALID_ARG),
@@ -296,7 +296,7 @@ def test_propagate_rejects_upsampled_problem():
     ((1, 0, 8, 256, 1 << 20), L.DOP_ERR_INVALID_ARG),      # nc < 1
     ((1, 64, 0, 256, 1 << 20), L.DOP_ERR_UNSUPPORTED),     # s < 1
     ((1, 64, 17, 256, 1 << 20), L.DOP_ERR_UNSUPPORTED),    # s > 16
-    ((0, 8192, 16, 256, 1 << 30), L.DOP_ERR_UNSUPPORTED),  # nc s > 65536
+    ((0, 16384, 16, 256, 1 << 30), L.DOP_ERR_UNSUPPORTED),  # nc s > 131072
     ((0, 64, 8, 0, 1 << 20), L.DOP_ERR_INVALID_ARG),       # NULL input
     ((0, 64, 8, 258, 1 << 20), L.DOP_ERR_INVALID_ARG),     # misaligned
     ((0, 64, 8, 1 << 20, (1 << 20) + 4096), L.DOP_ERR_INVALID_ARG),  # overlap

@@ -1,14 +1,20 @@
-"""Write tests/golden/psf_large_550nm_rows.npz with the FP64 oracle only.
+"""Write the full-size PSF goldens of the large workload with the FP64 oracle
+only.
 
-Eq. (1)-(4) at the large workload's full size for one of its wavelengths:
-the seeded 32768^2 height map (16-level f = 50 mm lens plus smooth noise),
-pitch 0.5 um, z = 50 mm, padded to 65536^2, lambda = 550 nm with its Cauchy
-index.  Stores 12 whole rows of the N x N crop PSF (rounded to float32), the
-row indices, and the PSF's total and maximum over the crop (float64).
+Eq. (1)-(4) at the large workload's full size: the seeded 32768^2 height map
+(16-level f = 50 mm lens plus smooth noise), pitch 0.5 um, z = 50 mm, padded
+to 65536^2, with the Cauchy index.  Each file stores 12 whole rows of the
+N x N crop PSF (rounded to float32), the row indices, and the PSF's total and
+maximum over the crop (float64).
+
+    psf_large_550nm_rows.npz   one wavelength, 550 nm
+    psf_large_3lam_rows.npz    the sum over 400, 550 and 700 nm (the ends and
+                               the middle of the band; at 700 nm the corner
+                               bins come within 2 % of the evanescent edge)
 
 Needs about 90 GB of host memory (one complex128 65536^2 array plus blocks):
 
-    python tests/golden/make_large_psf_golden.py [out.npz]    (a few minutes)
+    python tests/golden/make_large_psf_golden.py [out_dir]   (a minute per wavelength)
 """
 
 import os
@@ -24,7 +30,7 @@ import oracle  # noqa: E402
 from oracle import asm  # noqa: E402
 from paper_2505_22313_amd import workloads as wl  # noqa: E402
 
-K_INDEX = 15  # 550 nm in the large workload's 400..700 nm sweep
+SETS = {"psf_large_550nm_rows.npz": [15], "psf_large_3lam_rows.npz": [0, 15, 30]}
 
 
 def rows_of(n):
@@ -33,7 +39,7 @@ def rows_of(n):
                     dtype=np.int64)
 
 
-def main(out_path):
+def main(out_dir):
     asm.WORKERS = min(16, os.cpu_count() or 1)
     t0 = time.time()
 
@@ -41,17 +47,22 @@ def main(out_path):
         print(f"[{time.time() - t0:7.1f}s] {msg}", flush=True)
 
     p = wl.problem("large")
-    lam, nidx = float(p["lams"][K_INDEX]), float(p["n_index"][K_INDEX])
-    assert abs(lam - 0.55) < 1e-12
     h = wl.heights("large")
     log(f"heights {h.shape} {h.dtype}")
-    psf = oracle.psf_lowmem(h, p["dx"], p["z"], p["m"], lam, nidx, log=log)
     rows = rows_of(p["n"])
-    np.savez(out_path, rows=rows, psf_rows=psf[rows].astype(np.float32),
-             total=np.float64(psf.sum()), peak=np.float64(psf.max()),
-             n=p["n"], m=p["m"], dx=p["dx"], z=p["z"], lam=lam, n_index=nidx)
-    log(f"wrote {out_path}")
+    psf = {}
+    for k in sorted({k for ks in SETS.values() for k in ks}):
+        log(f"lambda {p['lams'][k]}")
+        psf[k] = oracle.psf_lowmem(h, p["dx"], p["z"], p["m"], float(p["lams"][k]),
+                                   float(p["n_index"][k]), log=log)
+    for name, ks in SETS.items():
+        acc = psf[ks[0]] if len(ks) == 1 else sum(psf[k] for k in ks)  # k order
+        np.savez(os.path.join(out_dir, name), rows=rows, psf_rows=acc[rows].astype(np.float32),
+                 total=np.float64(acc.sum()), peak=np.float64(acc.max()), n=p["n"], m=p["m"],
+                 dx=p["dx"], z=p["z"], lams=np.array([p["lams"][k] for k in ks]),
+                 n_index=np.array([p["n_index"][k] for k in ks]))
+        log(f"wrote {name}")
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else os.path.join(HERE, "psf_large_550nm_rows.npz"))
+    main(sys.argv[1] if len(sys.argv) > 1 else HERE)

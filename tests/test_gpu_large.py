@@ -145,17 +145,16 @@ def test_lens_focus_large(api):
     torch.cuda.empty_cache()
 
 
-LARGE_PSF = os.path.join(os.path.dirname(__file__), "golden", "psf_large_550nm_rows.npz")
-
-
-def test_large_workload_psf_rows_vs_oracle(api):
+@pytest.mark.parametrize("golden", ["psf_large_550nm_rows.npz", "psf_large_3lam_rows.npz"])
+def test_large_workload_psf_rows_vs_oracle(api, golden):
     """The large workload itself (seeded 32768^2 lens + noise heights, 65536^2
-    grid) at 550 nm: 12 whole rows of the PSF against the FP64 oracle
-    (tests/golden/make_large_psf_golden.py), plus the crop's total and peak."""
-    g = np.load(LARGE_PSF)
+    grid) at 550 nm, and summed over 400, 550 and 700 nm: 12 whole rows of
+    the PSF against the FP64 oracle (tests/golden/make_large_psf_golden.py),
+    plus the crop's total and peak."""
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", golden))
     assert (int(g["n"]), int(g["m"]), float(g["dx"]), float(g["z"])) == (N, M, DX, Z)
     h = torch.from_numpy(wl.heights("large")).cuda()
-    prob = api.Problem(N, M, DX, Z, [float(g["lam"])], [float(g["n_index"])])
+    prob = api.Problem(N, M, DX, Z, g["lams"], g["n_index"])
     out = api.psf(h, prob)
     got = out[torch.from_numpy(g["rows"]).cuda()].double().cpu().numpy()
     assert rel(got, g["psf_rows"].astype(np.float64)) < 1e-4

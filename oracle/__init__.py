@@ -12,6 +12,10 @@ Parity status per function (see the module docstrings for the passages):
   ``propagate``, ``psf``, ``psf_backward``: pinned (brute-force DFT on tiny
   grids, Parseval, z = 0, +-z round trip, plane-wave eigenfunction,
   sinc^2 / Airy lens focus, finite differences, adjoint dot product).
+* rectangular grids (``m`` = (My, Mx), DOE Ny x Nx) in all of the above:
+  pinned (matrix DFT, per-bin brute-force sums, Parseval, z = 0, +-z round
+  trip, the rectangular pupil's focal spot with its two widths, the per-axis
+  band limit, the gradient against finite differences).
 * ``psf_lowmem`` (one wavelength, blocked for memory): pinned to ``psf`` at
   small sizes (same values to rounding), and through it to the pins above.
 * ``band_limit`` and the ``bandlimit`` option: pinned (reduces to plain ASM
@@ -28,6 +32,7 @@ from .asm import (  # noqa: F401
     direct_dft2,
     doe_field,
     embed,
+    grid_shape,
     pad_offset,
     propagate,
     propagate_padded,

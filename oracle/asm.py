@@ -18,6 +18,9 @@ The model (paper Sec. 3.1, "Fabrication-aware Image Formation Model"):
 * Eq. (4): the intensity |E_dest|^2 is summed over wavelengths.
 * The DOE (N x N samples) is zero-padded to an M x M grid, centred at offset
   p0 = (M - N) // 2 (the paper's grids are twice the DOE extent, Table 2).
+  Grids may be rectangular (the paper's largest is 128,640 x 85,760): arrays
+  are (rows, columns) = (y, x), ``m`` is an int or a (My, Mx) pair, and every
+  axis is padded, transformed and sampled in frequency on its own.
 
 Every array here is complex128 / float64.  ``scipy.fft`` is used as the FFT
 primitive; ``direct_dft2`` and ``brute_propagate`` are the independent
@@ -44,6 +47,14 @@ def pad_offset(n, m):
     return (m - n) // 2
 
 
+def grid_shape(m):
+    """(My, Mx) of a padded grid given as an int (square) or a pair."""
+    if np.ndim(m) == 0:
+        return int(m), int(m)
+    my, mx = m
+    return int(my), int(mx)
+
+
 def doe_field(h, lam, n_index, amp=None):
     """Eq. (1)-(2): E = amp * exp(i * 2*pi/lam * (n - 1) * h), complex128."""
     h = np.asarray(h, dtype=np.float64)
@@ -55,18 +66,22 @@ def doe_field(h, lam, n_index, amp=None):
 
 
 def embed(e, m):
-    """Zero-pad an N x N field into an M x M grid at offset p0 on both axes."""
-    n = e.shape[0]
-    p0 = pad_offset(n, m)
-    ep = np.zeros((m, m), dtype=np.complex128)
-    ep[p0:p0 + n, p0:p0 + n] = e
+    """Zero-pad an Ny x Nx field into an My x Mx grid at offset
+    p0 = (M - N) // 2 on each axis."""
+    ny, nx = e.shape
+    my, mx = grid_shape(m)
+    py, px = pad_offset(ny, my), pad_offset(nx, mx)
+    ep = np.zeros((my, mx), dtype=np.complex128)
+    ep[py:py + ny, px:px + nx] = e
     return ep
 
 
 def crop(u, n):
-    """The N x N window [p0, p0 + N)^2 of an M x M grid."""
-    p0 = pad_offset(n, u.shape[0])
-    return u[p0:p0 + n, p0:p0 + n]
+    """The window of N samples at offset p0 on each axis of a padded grid;
+    n is an int (square window) or an (Ny, Nx) pair."""
+    ny, nx = grid_shape(n)
+    py, px = pad_offset(ny, u.shape[0]), pad_offset(nx, u.shape[1])
+    return u[py:py + ny, px:px + nx]
 
 
 def band_limit(m, dx, lam, z):
@@ -81,25 +96,28 @@ def band_limit(m, dx, lam, z):
 def transfer_function(m, dx, lam, z, bandlimit=False):
     """Angular-spectrum transfer function on the FFT frequency grid (Eq. 3).
 
-    Frequencies are numpy's fftfreq (k / (M dx), k signed).  Rows index fy,
-    columns index fx.  A frequency propagates iff s < 1 with
+    Frequencies are numpy's fftfreq (k / (M dx), k signed), per axis.  Rows
+    index fy, columns index fx.  A frequency propagates iff s < 1 with
     s = (lam*fx)^2 + (lam*fy)^2, each square and the sum rounded once in FP64.
-    With ``bandlimit`` it must also satisfy |fx| < f_lim and |fy| < f_lim
-    (band-limited ASM, one of the propagation variants the paper cites).
+    With ``bandlimit`` it must also satisfy |fx| < f_lim(Mx) and
+    |fy| < f_lim(My) (band-limited ASM, one of the propagation variants the
+    paper cites; the limit depends on the axis length).
     """
-    return transfer_rows(m, dx, lam, z, 0, m, bandlimit=bandlimit)
+    return transfer_rows(m, dx, lam, z, 0, grid_shape(m)[0], bandlimit=bandlimit)
 
 
 def transfer_rows(m, dx, lam, z, r0, r1, bandlimit=False):
     """Rows r0 .. r1-1 (fy bins) of ``transfer_function``."""
-    f = np.fft.fftfreq(m, d=dx)
-    a = lam * f
-    a2 = a * a
-    s = a2[r0:r1, None] + a2[None, :]
+    my, mx = grid_shape(m)
+    fy = np.fft.fftfreq(my, d=dx)
+    fx = np.fft.fftfreq(mx, d=dx)
+    ay, ax = lam * fy, lam * fx
+    s = (ay * ay)[r0:r1, None] + (ax * ax)[None, :]
     prop = s < 1.0
     if bandlimit:
-        inside = np.abs(f) < band_limit(m, dx, lam, z)
-        prop = prop & inside[r0:r1, None] & inside[None, :]
+        in_y = np.abs(fy) < band_limit(my, dx, lam, z)
+        in_x = np.abs(fx) < band_limit(mx, dx, lam, z)
+        prop = prop & in_y[r0:r1, None] & in_x[None, :]
     root = np.sqrt(np.where(prop, 1.0 - s, 0.0))
     kz = 2.0 * np.pi * z / lam
     return np.where(prop, np.exp(1j * (kz * root)), 0.0 + 0.0j)
@@ -110,8 +128,7 @@ def propagate_padded(ep, dx, lam, z, adjoint=False, bandlimit=False):
 
     ``adjoint=True`` applies the adjoint operator ifft2(fft2(ep) * conj(H)).
     """
-    m = ep.shape[0]
-    h = transfer_function(m, dx, lam, z, bandlimit=bandlimit)
+    h = transfer_function(ep.shape, dx, lam, z, bandlimit=bandlimit)
     if adjoint:
         h = np.conj(h)
     a = sfft.fft2(ep, workers=WORKERS)
@@ -125,7 +142,7 @@ def propagate(u_in, m, dx, lam, z, out_mode="crop", adjoint=False, bandlimit=Fal
     M x M plane (``out_mode="full"``).
     """
     u_in = np.asarray(u_in, dtype=np.complex128)
-    n = u_in.shape[0]
+    n = u_in.shape
     u = propagate_padded(embed(u_in, m), dx, lam, z, adjoint=adjoint, bandlimit=bandlimit)
     return crop(u, n) if out_mode == "crop" else u
 
@@ -139,11 +156,10 @@ def psf(h, dx, z, m, lams, n_index, weights=None, amp=None, out_mode="crop",
     (same region as the PSF).
     """
     h = np.asarray(h, dtype=np.float64)
-    n = h.shape[0]
     k_count = len(lams)
     if weights is None:
         weights = np.ones(k_count)
-    shape = (n, n) if out_mode == "crop" else (m, m)
+    shape = h.shape if out_mode == "crop" else grid_shape(m)
     acc = np.zeros(shape, dtype=np.float64)
     fields = []
     for k in range(k_count):
@@ -157,7 +173,8 @@ def psf(h, dx, z, m, lams, n_index, weights=None, amp=None, out_mode="crop",
 
 def psf_lowmem(h, dx, z, m, lam, n_index, block=1024, log=None):
     """``psf`` for one wavelength (CROP, no amplitude mask, weight 1) on grids
-    whose full-plane temporaries do not fit in memory.
+    whose full-plane temporaries do not fit in memory (square or
+    rectangular).
 
     Same definition, same order of operations per element: the 2-D DFTs are
     taken as 1-D DFTs along rows and then along columns (the 2-D DFT is
@@ -168,36 +185,37 @@ def psf_lowmem(h, dx, z, m, lam, n_index, block=1024, log=None):
     16 M^2 bytes plus a few blocks.  Returns the N x N float64 PSF.
     """
     h = np.asarray(h)
-    n = h.shape[0]
-    p0 = pad_offset(n, m)
+    ny, nx = h.shape
+    my, mx = grid_shape(m)
+    py, px = pad_offset(ny, my), pad_offset(nx, mx)
     say = log or (lambda msg: None)
-    ep = np.zeros((m, m), dtype=np.complex128)
-    for r0 in range(0, n, block):
-        r1 = min(n, r0 + block)
-        rows = ep[p0 + r0:p0 + r1]
-        rows[:, p0:p0 + n] = doe_field(h[r0:r1], lam, n_index)
-        ep[p0 + r0:p0 + r1] = sfft.fft(rows, axis=1, workers=WORKERS)
+    ep = np.zeros((my, mx), dtype=np.complex128)
+    for r0 in range(0, ny, block):
+        r1 = min(ny, r0 + block)
+        rows = ep[py + r0:py + r1]
+        rows[:, px:px + nx] = doe_field(h[r0:r1], lam, n_index)
+        ep[py + r0:py + r1] = sfft.fft(rows, axis=1, workers=WORKERS)
     say("row DFTs done")
-    for c0 in range(0, m, block):
-        c1 = min(m, c0 + block)
+    for c0 in range(0, mx, block):
+        c1 = min(mx, c0 + block)
         ep[:, c0:c1] = sfft.fft(ep[:, c0:c1], axis=0, workers=WORKERS)
     say("column DFTs done")
     def apply_h(r0):
-        r1 = min(m, r0 + hblock)
-        ep[r0:r1] *= transfer_rows(m, dx, lam, z, r0, r1)
+        r1 = min(my, r0 + hblock)
+        ep[r0:r1] *= transfer_rows((my, mx), dx, lam, z, r0, r1)
 
-    hblock = max(1, min(block, (1 << 24) // m))  # about 1 GB of temporaries per thread
+    hblock = max(1, min(block, (1 << 24) // mx))  # about 1 GB of temporaries per thread
     with ThreadPoolExecutor(WORKERS) as pool:
-        list(pool.map(apply_h, range(0, m, hblock)))
+        list(pool.map(apply_h, range(0, my, hblock)))
     say("transfer function applied")
-    for c0 in range(0, m, block):
-        c1 = min(m, c0 + block)
+    for c0 in range(0, mx, block):
+        c1 = min(mx, c0 + block)
         ep[:, c0:c1] = sfft.ifft(ep[:, c0:c1], axis=0, workers=WORKERS)
     say("inverse column DFTs done")
-    out = np.empty((n, n), dtype=np.float64)
-    for r0 in range(0, n, block):
-        r1 = min(n, r0 + block)
-        u = sfft.ifft(ep[p0 + r0:p0 + r1], axis=1, workers=WORKERS)[:, p0:p0 + n]
+    out = np.empty((ny, nx), dtype=np.float64)
+    for r0 in range(0, ny, block):
+        r1 = min(ny, r0 + block)
+        u = sfft.ifft(ep[py + r0:py + r1], axis=1, workers=WORKERS)[:, px:px + nx]
         out[r0:r1] = u.real * u.real + u.imag * u.imag
     say("inverse row DFTs done")
     return out
@@ -216,11 +234,11 @@ def psf_backward(h, dx, z, m, lams, n_index, grad_psf, weights=None, amp=None,
     """
     h = np.asarray(h, dtype=np.float64)
     g = np.asarray(grad_psf, dtype=np.float64)
-    n = h.shape[0]
+    n = h.shape
     k_count = len(lams)
     if weights is None:
         weights = np.ones(k_count)
-    grad = np.zeros((n, n), dtype=np.float64)
+    grad = np.zeros(n, dtype=np.float64)
     for k in range(k_count):
         e = doe_field(h, lams[k], n_index[k], amp)
         ep = embed(e, m)
@@ -241,18 +259,21 @@ def psf_backward(h, dx, z, m, lams, n_index, grad_psf, weights=None, amp=None,
 # ---------------------------------------------------------------------------
 
 def direct_dft2(x, inverse=False):
-    """2-D DFT written as the matrix product W x W^T (no FFT).
+    """2-D DFT written as the matrix product Wy x Wx^T (no FFT).
 
-    Forward: X[u, v] = sum_{y, x} x[y, x] exp(-2 pi i (u y + v x) / M).
-    Inverse: the conjugate kernel and a 1/M^2 factor.
+    Forward: X[u, v] = sum_{y, x} x[y, x] exp(-2 pi i (u y / My + v x / Mx)).
+    Inverse: the conjugate kernels and a 1/(My Mx) factor.
     """
     x = np.asarray(x, dtype=np.complex128)
-    m = x.shape[0]
-    idx = np.arange(m)
+    my, mx = x.shape
     sign = 1.0 if inverse else -1.0
-    w = np.exp(sign * 2j * np.pi * np.outer(idx, idx) / m)
-    out = w @ x @ w.T
-    return out / (m * m) if inverse else out
+
+    def kernel(m):
+        idx = np.arange(m)
+        return np.exp(sign * 2j * np.pi * np.outer(idx, idx) / m)
+
+    out = kernel(my) @ x @ kernel(mx).T
+    return out / (my * mx) if inverse else out
 
 
 def _signed_freq(k, m, dx):
@@ -267,25 +288,26 @@ def brute_propagate(u_in, m, dx, lam, z):
 
     Every bin's transfer value is evaluated on its own from the physical
     frequency, the spectrum and its inverse are plain double sums.  Returns the
-    full M x M field for a centred N x N input.
+    full My x Mx field for a centred Ny x Nx input (m an int or (My, Mx)).
     """
-    ep = embed(np.asarray(u_in, dtype=np.complex128), m)
-    idx = np.arange(m)
-    u_out = np.zeros((m, m), dtype=np.complex128)
-    for fu in range(m):
-        fy = _signed_freq(fu, m, dx)
-        for fv in range(m):
-            fx = _signed_freq(fv, m, dx)
+    my, mx = grid_shape(m)
+    ep = embed(np.asarray(u_in, dtype=np.complex128), (my, mx))
+    iy, ix = np.arange(my), np.arange(mx)
+    u_out = np.zeros((my, mx), dtype=np.complex128)
+    for fu in range(my):
+        fy = _signed_freq(fu, my, dx)
+        for fv in range(mx):
+            fx = _signed_freq(fv, mx, dx)
             s = (lam * fx) * (lam * fx) + (lam * fy) * (lam * fy)
             if not s < 1.0:
                 continue
             hval = np.exp(1j * 2.0 * np.pi * z * np.sqrt(1.0 / (lam * lam) - fx * fx - fy * fy))
             # forward DFT coefficient of bin (fu, fv)
-            ky = np.exp(-2j * np.pi * fu * idx / m)
-            kx = np.exp(-2j * np.pi * fv * idx / m)
+            ky = np.exp(-2j * np.pi * fu * iy / my)
+            kx = np.exp(-2j * np.pi * fv * ix / mx)
             coef = ky @ ep @ kx
             # add this bin's plane wave to the output
-            u_out += (coef * hval / (m * m)) * np.outer(np.conj(ky), np.conj(kx))
+            u_out += (coef * hval / (my * mx)) * np.outer(np.conj(ky), np.conj(kx))
     return u_out
 
 

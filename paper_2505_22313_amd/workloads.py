@@ -55,10 +55,19 @@ def cauchy_index(lam_um):
     return 1.45 + 3.6e-3 / (lam * lam)
 
 
+def shape2(n):
+    """(rows, columns) of a DOE given as an int (square) or a pair."""
+    if np.ndim(n) == 0:
+        return int(n), int(n)
+    ny, nx = n
+    return int(ny), int(nx)
+
+
 def uniform_heights(n, seed, hmax=1.2):
-    """i.i.d. uniform heights in [0, hmax] um, float32 (PCG64 stream `seed`)."""
+    """i.i.d. uniform heights in [0, hmax] um, float32 (PCG64 stream `seed`);
+    n is an int (square) or (rows, columns)."""
     rng = np.random.default_rng(seed)
-    return rng.uniform(0.0, hmax, size=(n, n)).astype(np.float32)
+    return rng.uniform(0.0, hmax, size=shape2(n)).astype(np.float32)
 
 
 def pixel_coords(n, dx):
@@ -71,16 +80,18 @@ def fresnel_lens_heights(n, dx, f, lam0=LAMBDA0, levels=0, row_block=2048):
 
     phi(r) = -(2 pi / lam0) (sqrt(r^2 + f^2) - f), wrapped into [0, 2 pi),
     h = phi_w * lam0 / (2 pi (n(lam0) - 1)).  With ``levels > 0`` the height
-    is quantised to that many uniform levels (floor).  float32 result.
+    is quantised to that many uniform levels (floor).  float32 result; n is
+    an int (square) or (rows, columns).
     """
     n0 = float(cauchy_index(lam0))
     hmax = lam0 / (n0 - 1.0)
-    c = pixel_coords(n, dx)
-    out = np.empty((n, n), dtype=np.float32)
-    x2 = c * c
+    ny, nx = shape2(n)
+    out = np.empty((ny, nx), dtype=np.float32)
+    y2 = pixel_coords(ny, dx) ** 2
+    x2 = pixel_coords(nx, dx) ** 2
 
     def rows(r0, r1):
-        r2 = x2[r0:r1, None] + x2[None, :]
+        r2 = y2[r0:r1, None] + x2[None, :]
         turns = -(np.sqrt(r2 + f * f) - f) / lam0
         frac = turns - np.floor(turns)  # wrapped phase / (2 pi), in [0, 1)
         h = frac * hmax
@@ -89,7 +100,7 @@ def fresnel_lens_heights(n, dx, f, lam0=LAMBDA0, levels=0, row_block=2048):
             h = np.floor(h / step) * step
         out[r0:r1] = h.astype(np.float32)
 
-    _parallel_rows(n, min(row_block, 512), rows)
+    _parallel_rows(ny, min(row_block, 512), rows)
     return out
 
 
@@ -152,9 +163,10 @@ def circular_aperture(n, dx, radius):
 
 def ideal_lens_heights(n, dx, f, lam, n_index):
     """Unwrapped hyperbolic lens for wavelength lam, as heights modulo one
-    wave (float32): phase -(2 pi/lam)(sqrt(r^2+f^2)-f) mod 2 pi."""
-    c = pixel_coords(n, dx)
-    r2 = c[:, None] ** 2 + c[None, :] ** 2
+    wave (float32): phase -(2 pi/lam)(sqrt(r^2+f^2)-f) mod 2 pi; n is an int
+    (square) or (rows, columns)."""
+    ny, nx = shape2(n)
+    r2 = pixel_coords(ny, dx)[:, None] ** 2 + pixel_coords(nx, dx)[None, :] ** 2
     turns = -(np.sqrt(r2 + f * f) - f) / lam
     frac = turns - np.floor(turns)
     return (frac * lam / (n_index - 1.0)).astype(np.float32)

@@ -460,3 +460,112 @@ def test_wrapped_lens_first_order_efficiency(lam, levels):
     alpha = lam0 * (nl - 1.0) / (lam * (n0 - 1.0))
     eta = np.sinc(1.0 - alpha) ** 2 * (np.sinc(1.0 / levels) ** 2 if levels else 1.0)
     assert abs(i_lens / i_ideal / eta - 1.0) < 0.01
+
+
+# ---------------------------------------------------------------------------
+# Rectangular grids (the paper's largest grid is 128,640 x 85,760): every axis
+# is padded and sampled in frequency on its own.  An axis mix-up (fx and fy
+# swapped, one axis's M used for the other) fails the brute-force sums and
+# the rectangular focal spot below.
+# ---------------------------------------------------------------------------
+
+def rand_rect(rng, ny, nx):
+    return rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx))
+
+
+@pytest.mark.parametrize("my,mx", [(8, 12), (12, 8), (16, 24), (10, 32)])
+def test_rect_fft_path_matches_direct_dft(my, mx):
+    rng = np.random.default_rng(my * 100 + mx)
+    ep = rand_rect(rng, my, mx)
+    dx, lam, z = 0.3, 0.5, 7.0
+    h = oracle.transfer_function((my, mx), dx, lam, z)
+    assert h.shape == (my, mx)
+    want = asm.direct_dft2(asm.direct_dft2(ep) * h, inverse=True)
+    got = oracle.propagate_padded(ep, dx, lam, z)
+    assert rel(got, want) < 1e-12
+
+
+@pytest.mark.parametrize("my,mx,ny,nx,dx,lam,z", [
+    (8, 12, 5, 7, 0.3, 0.5, 3.0),      # evanescent corners on both axes
+    (12, 8, 7, 4, 0.3, 0.5, 4.0),
+    (10, 16, 10, 9, 0.27, 0.5, 6.0),   # no padding along y
+    (16, 6, 9, 6, 1.0, 0.55, 30.0),    # all bins propagate
+])
+def test_rect_propagate_matches_brute_force(my, mx, ny, nx, dx, lam, z):
+    rng = np.random.default_rng(my + mx + ny + nx)
+    u = rand_rect(rng, ny, nx)
+    got = oracle.propagate(u, (my, mx), dx, lam, z, out_mode="full")
+    want = asm.brute_propagate(u, (my, mx), dx, lam, z)
+    assert got.shape == (my, mx)
+    assert rel(got, want) < 1e-11
+    crop = oracle.propagate(u, (my, mx), dx, lam, z)
+    py, px = (my - ny) // 2, (mx - nx) // 2
+    assert np.array_equal(crop, got[py:py + ny, px:px + nx])
+
+
+def test_rect_parseval_z0_and_round_trip():
+    ny, nx, my, mx, dx, lam, z = 40, 72, 96, 144, 1.0, 0.55, 3000.0
+    rng = np.random.default_rng(21)
+    u = rand_rect(rng, ny, nx)
+    p = oracle.psf(wl.uniform_heights((ny, nx), seed=22), dx, z, (my, mx), [lam], [1.46],
+                   out_mode="full")
+    assert p.shape == (my, mx) and abs(p.sum() / (ny * nx) - 1.0) < 1e-12
+    assert rel(oracle.propagate(u, (my, mx), dx, lam, 0.0, out_mode="full"),
+               oracle.embed(u, (my, mx))) < 1e-14
+    fwd = oracle.propagate(u, (my, mx), dx, lam, z, out_mode="full")
+    assert rel(oracle.propagate_padded(fwd, dx, lam, -z), oracle.embed(u, (my, mx))) < 1e-12
+
+
+def test_rect_lens_focus_sinc2():
+    """Rectangular pupil Ly x Lx focused at f: peak (Ly Lx/(lam f))^2 and the
+    focal profile sinc^2(Lx x/(lam f)) along x, sinc^2(Ly y/(lam f)) along y,
+    each with its own width (Fresnel numbers 24 and 54, as the square case)."""
+    ny, nx, dx, lam, f, nn = 512, 768, 1.0, 0.55, 5000.0, 1.5
+    h = wl.ideal_lens_heights((ny, nx), dx, f, lam, nn).astype(np.float64)
+    p = oracle.psf(h, dx, f, (2 * ny, 2 * nx), [lam], [nn])
+    cy, cx = ny // 2, nx // 2
+    ly, lx = ny * dx, nx * dx
+    i0 = (ly * lx / (lam * f)) ** 2
+    assert abs(p[cy, cx] / i0 - 1.0) < 0.02
+    assert np.unravel_index(np.argmax(p), p.shape) == (cy, cx)
+    t = np.arange(-12, 13) * dx
+    assert np.max(np.abs(p[cy, cx - 12:cx + 13] - i0 * np.sinc(lx * t / (lam * f)) ** 2)) / i0 < 0.02
+    assert np.max(np.abs(p[cy - 12:cy + 13, cx] - i0 * np.sinc(ly * t / (lam * f)) ** 2)) / i0 < 0.02
+
+
+def test_rect_bandlimit_mask_per_bin():
+    """Each axis gets the band limit of its own length."""
+    my, mx, dx, lam, z = 24, 40, 0.4, 0.6, 150.0
+    hb = oracle.transfer_function((my, mx), dx, lam, z, bandlimit=True)
+    fly = 1.0 / (lam * np.sqrt((2.0 * z / (my * dx)) ** 2 + 1.0))
+    flx = 1.0 / (lam * np.sqrt((2.0 * z / (mx * dx)) ** 2 + 1.0))
+    assert fly != flx
+    for fu in range(my):
+        for fv in range(mx):
+            fy, fx = asm._signed_freq(fu, my, dx), asm._signed_freq(fv, mx, dx)
+            keep = ((lam * fx) ** 2 + (lam * fy) ** 2 < 1.0 and abs(fx) < flx and abs(fy) < fly)
+            assert (hb[fu, fv] != 0) == keep
+
+
+def test_rect_gradient_adjoint_dot_product():
+    """<J dh, G> = <dh, J^T G> for the rectangular PSF's Jacobian J: finite
+    differences of the loss along a random direction against the gradient."""
+    ny, nx, my, mx, dx, z = 12, 20, 24, 32, 0.5, 40.0
+    lams, nidx = [0.5, 0.62], [1.46, 1.455]
+    rng = np.random.default_rng(23)
+    h = rng.uniform(0, 1.2, (ny, nx))
+    g = rng.standard_normal((ny, nx))
+    d = rng.standard_normal((ny, nx))
+    grad = oracle.psf_backward(h, dx, z, (my, mx), lams, nidx, g)
+    eps = 1e-6
+    lp = np.sum(g * oracle.psf(h + eps * d, dx, z, (my, mx), lams, nidx))
+    lm = np.sum(g * oracle.psf(h - eps * d, dx, z, (my, mx), lams, nidx))
+    fd = (lp - lm) / (2 * eps)
+    assert abs(fd - np.sum(grad * d)) < 1e-6 * abs(fd)
+
+
+def test_rect_psf_lowmem_equals_psf():
+    h = np.random.default_rng(24).uniform(0, 1.2, (40, 72))
+    a = oracle.psf(h, 0.5, 300.0, (96, 160), [0.55], [1.46])
+    b = oracle.psf_lowmem(h, 0.5, 300.0, (96, 160), 0.55, 1.46, block=16)
+    assert rel(b, a) < 1e-12

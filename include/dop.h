@@ -93,12 +93,17 @@ enum { DOP_OP_PROPAGATE = 0, DOP_OP_PSF = 1, DOP_OP_PSF_BACKWARD = 2 };
  * distance, padding).  Host arrays are read during the call only.
  */
 typedef struct {
-  int32_t n;             /* DOE grid n x n, 1 <= n <= m                       */
-  int32_t m;             /* padded FFT grid m x m: a power of two in
-                            16..131072 (137 GB of workspace at 131072), or
-                            one of the grids 240, 720, 1440,
-                            3072, 3600, 28800 (= 2^7 3^2 5^2) and 40000
-                            (= 2^6 5^4, the paper's Table 2 grids)         */
+  int32_t n;             /* DOE columns (n x n when ny = 0), 1 <= n <= m     */
+  int32_t m;             /* padded FFT grid columns (m x m when my = 0).
+                            Square grids: a power of two in 16..131072
+                            (137 GB of workspace at 131072), or 240, 720,
+                            1440, 3072, 3600, 28800 (= 2^7 3^2 5^2), 40000
+                            (= 2^6 5^4) and 2144 (= 2^5 67).
+                            Rectangular grids (my rows x m columns):
+                            720 x 240, 512 x 2048, 240 x 2144, 5360 x 240,
+                            16080 x 10720 and 128640 x 85760 (the paper's
+                            largest, Table 2: 2^7 3 5 67 x 2^8 5 67, an
+                            88 GB workspace).                             */
   double dx;             /* sampling pitch (> 0)                              */
   double z;              /* propagation distance (any sign, 0 allowed)        */
   int32_t n_lambda;      /* K, 1..DOP_MAX_LAMBDA                              */
@@ -115,6 +120,12 @@ typedef struct {
                             stays n x n; dop_psf_backward returns the
                             gradient on the coarse grid.  dop_propagate
                             requires 0 or 1.                               */
+  int32_t ny;            /* DOE rows; 0 means ny = n.  1 <= ny <= my        */
+  int32_t my;            /* padded grid rows; 0 means my = m.  Arrays are
+                            row-major (x fastest): the DOE is ny x n, a full
+                            plane my x m, and every axis is padded by
+                            p0 = (M - N) / 2 on its own (Sec. 3.1 with the
+                            rectangular grid of Table 2).                  */
 } dop_problem;
 
 typedef struct dop_context dop_context;

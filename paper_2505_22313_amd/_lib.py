@@ -53,6 +53,8 @@ class DopProblem(ctypes.Structure):
         ("out_mode", ctypes.c_int32),
         ("flags", ctypes.c_int32),
         ("upsample", ctypes.c_int32),
+        ("ny", ctypes.c_int32),
+        ("my", ctypes.c_int32),
     ]
 
 

@@ -18,16 +18,27 @@ from ._lib import DopError, DopProblem, DopServeStats, check, lib
 OUT_MODES = {"crop": L.DOP_OUT_CROP, "full": L.DOP_OUT_FULL}
 
 
+def _pair(v):
+    if np.ndim(v) == 0:
+        return int(v), int(v)
+    a, b = v
+    return int(a), int(b)
+
+
 class Problem:
     """Problem description (paper Sec. 3.1): DOE grid n x n, padded grid
     m x m, pitch dx, distance z, wavelengths, refractive indices n(lambda_k)
-    and PSF weights.  Lengths share one unit.  With upsample = s >= 2 the
-    height map (and its gradient) is the coarse (n/s) x (n/s) design,
-    nearest-neighbour upsampled to n x n inside the first pass."""
+    and PSF weights.  Lengths share one unit.  n and m may be (rows, columns)
+    pairs for a rectangular DOE and grid (Table 2's 128,640 x 85,760); the
+    attributes n and m are then the column counts.  With upsample = s >= 2
+    the height map (and its gradient) is the coarse design of 1/s the rows
+    and columns, nearest-neighbour upsampled inside the first pass."""
 
     def __init__(self, n, m, dx, z, lambdas, n_index, weights=None, out_mode="crop",
                  bandlimit=False, upsample=1):
-        self.n, self.m = int(n), int(m)
+        self.ny, self.nx = _pair(n)
+        self.my, self.mx = _pair(m)
+        self.n, self.m = self.nx, self.mx
         self.dx, self.z = float(dx), float(z)
         self.lambdas = np.ascontiguousarray(np.atleast_1d(lambdas), dtype=np.float64)
         self.n_index = np.ascontiguousarray(np.atleast_1d(n_index), dtype=np.float64)
@@ -43,7 +54,8 @@ class Problem:
         self.bandlimit = bool(bandlimit)
         self._c = DopProblem()
         c = self._c
-        c.n, c.m, c.dx, c.z = self.n, self.m, self.dx, self.z
+        c.n, c.m, c.dx, c.z = self.nx, self.mx, self.dx, self.z
+        c.ny, c.my = self.ny, self.my
         c.n_lambda = len(self.lambdas)
         c.lambda_ = self.lambdas.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         c.n_index = self.n_index.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
@@ -64,14 +76,22 @@ class Problem:
         return len(self.lambdas)
 
     @property
+    def doe_shape(self):
+        return (self.ny, self.nx)
+
+    @property
+    def grid_shape(self):
+        return (self.my, self.mx)
+
+    @property
     def h_shape(self):
         """Shape of the height map (the coarse design when upsampled)."""
-        nh = self.n // max(self.upsample, 1)
-        return (nh, nh)
+        s = max(self.upsample, 1)
+        return (self.ny // s, self.nx // s)
 
     @property
     def out_shape(self):
-        return (self.n, self.n) if self.out_mode == "crop" else (self.m, self.m)
+        return self.doe_shape if self.out_mode == "crop" else self.grid_shape
 
     def ptr(self):
         return ctypes.byref(self._c)
@@ -176,7 +196,7 @@ def propagate(u_in, prob, k=0, ctx=None, out=None):
     prob.lambdas[k].  Returns n x n (crop) or m x m (full) complex64."""
     ctx = ctx or default_context(u_in.device.index)
     dev = ctx.device
-    _need(u_in, "u_in", torch.complex64, (prob.n, prob.n), dev)
+    _need(u_in, "u_in", torch.complex64, prob.doe_shape, dev)
     if out is None:
         out = torch.empty(prob.out_shape, dtype=torch.complex64, device=u_in.device)
     _need(out, "out", torch.complex64, prob.out_shape, dev)
@@ -195,13 +215,13 @@ def psf(h, prob, amp=None, save_fields=False, ctx=None, out=None):
     dev = ctx.device
     _need(h, "h", torch.float32, prob.h_shape, dev)
     if amp is not None:
-        _need(amp, "amp", torch.float32, (prob.n, prob.n), dev)
+        _need(amp, "amp", torch.float32, prob.doe_shape, dev)
     if out is None:
         out = torch.empty(prob.out_shape, dtype=torch.float32, device=h.device)
     _need(out, "out", torch.float32, prob.out_shape, dev)
     saved = None
     if save_fields:
-        saved = torch.empty((prob.k, prob.n, prob.n), dtype=torch.complex64, device=h.device)
+        saved = torch.empty((prob.k,) + prob.doe_shape, dtype=torch.complex64, device=h.device)
     stream = _stream_handle(dev)
     nbytes = workspace_size(prob, L.DOP_OP_PSF)
     ws = ctx.workspace(nbytes, stream)
@@ -216,10 +236,10 @@ def psf_backward(h, prob, saved_u, grad_psf, amp=None, ctx=None, out=None):
     ctx = ctx or default_context(h.device.index)
     dev = ctx.device
     _need(h, "h", torch.float32, prob.h_shape, dev)
-    _need(saved_u, "saved_u", torch.complex64, (prob.k, prob.n, prob.n), dev)
-    _need(grad_psf, "grad_psf", torch.float32, (prob.n, prob.n), dev)
+    _need(saved_u, "saved_u", torch.complex64, (prob.k,) + prob.doe_shape, dev)
+    _need(grad_psf, "grad_psf", torch.float32, prob.doe_shape, dev)
     if amp is not None:
-        _need(amp, "amp", torch.float32, (prob.n, prob.n), dev)
+        _need(amp, "amp", torch.float32, prob.doe_shape, dev)
     if out is None:
         out = torch.empty(prob.h_shape, dtype=torch.float32, device=h.device)
     _need(out, "out", torch.float32, prob.h_shape, dev)
@@ -347,7 +367,7 @@ class Server:
             _need(h, "h", torch.float32, prob.h_shape, dev)
             _need(out, "out", torch.float32, prob.out_shape, dev)
             if amp is not None:
-                _need(amp, "amp", torch.float32, (prob.n, prob.n), dev)
+                _need(amp, "amp", torch.float32, prob.doe_shape, dev)
             hp, ap, op = _ptr(h), _ptr(amp), _ptr(out)
         check(lib().dop_serve_submit(self.handle, prob.ptr(), hp, ap, op, ctypes.byref(t)),
               "dop_serve_submit")

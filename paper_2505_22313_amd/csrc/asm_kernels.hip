@@ -194,6 +194,46 @@ struct UnitRoots<15> {
       -9.510565163e-01f, -7.431448255e-01f, -4.067366431e-01f};
 };
 
+template <>
+struct UnitRoots<67> {
+  static constexpr float c[67] = {
+      1.000000000e+00f, 9.956059820e-01f, 9.824625429e-01f, 9.606851876e-01f,
+      9.304652963e-01f, 8.920684426e-01f, 8.458320593e-01f, 7.921624734e-01f,
+      7.315313353e-01f, 6.644714734e-01f, 5.915722124e-01f, 5.134741935e-01f,
+      4.308637449e-01f, 3.444668503e-01f, 2.550427686e-01f, 1.633773618e-01f,
+      7.027618895e-02f, -2.344257360e-02f, -1.169553220e-01f, -2.094402628e-01f,
+      -3.000846350e-01f, -3.880918527e-01f, -4.726885052e-01f, -5.531311541e-01f,
+      -6.287128666e-01f, -6.987694278e-01f, -7.626851781e-01f, -8.198984237e-01f,
+      -8.699063724e-01f, -9.122695527e-01f, -9.466156753e-01f, -9.726429053e-01f,
+      -9.901225145e-01f, -9.989008915e-01f, -9.989008915e-01f, -9.901225145e-01f,
+      -9.726429053e-01f, -9.466156753e-01f, -9.122695527e-01f, -8.699063724e-01f,
+      -8.198984237e-01f, -7.626851781e-01f, -6.987694278e-01f, -6.287128666e-01f,
+      -5.531311541e-01f, -4.726885052e-01f, -3.880918527e-01f, -3.000846350e-01f,
+      -2.094402628e-01f, -1.169553220e-01f, -2.344257360e-02f, 7.027618895e-02f,
+      1.633773618e-01f, 2.550427686e-01f, 3.444668503e-01f, 4.308637449e-01f,
+      5.134741935e-01f, 5.915722124e-01f, 6.644714734e-01f, 7.315313353e-01f,
+      7.921624734e-01f, 8.458320593e-01f, 8.920684426e-01f, 9.304652963e-01f,
+      9.606851876e-01f, 9.824625429e-01f, 9.956059820e-01f};
+  static constexpr float s[67] = {
+      0.000000000e+00f, 9.364148953e-02f, 1.864600543e-01f, 2.776400014e-01f,
+      3.663800382e-01f, 4.519003140e-01f, 5.334492736e-01f, 6.103102618e-01f,
+      6.818078216e-01f, 7.473136296e-01f, 8.062520186e-01f, 8.581050359e-01f,
+      9.024169952e-01f, 9.387984816e-01f, 9.669297732e-01f, 9.865636511e-01f,
+      9.975275722e-01f, 9.997251851e-01f, 9.931371772e-01f, 9.778214440e-01f,
+      9.539125808e-01f, 9.216206996e-01f, 8.812295825e-01f, 8.330941882e-01f,
+      7.776375321e-01f, 7.153469695e-01f, 6.467699120e-01f, 5.725090173e-01f,
+      4.932168927e-01f, 4.095903603e-01f, 3.223643332e-01f, 2.323053566e-01f,
+      1.402048723e-01f, 4.687226247e-02f, -4.687226247e-02f, -1.402048723e-01f,
+      -2.323053566e-01f, -3.223643332e-01f, -4.095903603e-01f, -4.932168927e-01f,
+      -5.725090173e-01f, -6.467699120e-01f, -7.153469695e-01f, -7.776375321e-01f,
+      -8.330941882e-01f, -8.812295825e-01f, -9.216206996e-01f, -9.539125808e-01f,
+      -9.778214440e-01f, -9.931371772e-01f, -9.997251851e-01f, -9.975275722e-01f,
+      -9.865636511e-01f, -9.669297732e-01f, -9.387984816e-01f, -9.024169952e-01f,
+      -8.581050359e-01f, -8.062520186e-01f, -7.473136296e-01f, -6.818078216e-01f,
+      -6.103102618e-01f, -5.334492736e-01f, -4.519003140e-01f, -3.663800382e-01f,
+      -2.776400014e-01f, -1.864600543e-01f, -9.364148953e-02f};
+};
+
 // R = R1 * R2 from two in-register DFTs (four-step split n = n1 R2 + n2,
 // k = k1 + R1 k2, twiddles omega_R^(n2 k1) from UnitRoots<R>).
 template <int R1, int R2, bool INV>
@@ -266,12 +306,14 @@ struct Dft {
 };
 
 // ---------------------------------------------------------------------------
-// Stockham stage plan for an L-point DFT, L = 2^a 3^b 5^c <= 1024: the
+// Stockham stage plan for an L-point DFT, L = 2^a 3^b 5^c 67^d <= 1024: the
 // power-of-two factor in radix 16/8/4 stages (as for a power-of-two L), then
 // the odd factor: a radix-15 stage per (3, 5) pair, radix 9 per pair of the
-// remaining threes, radix 5 per remaining five, a last radix 3.  (Radix 25
-// would save more stages, but 25 points per item plus the prefetched inputs
-// overflow the 128 registers a thread has at this occupancy.)
+// remaining threes, radix 5 per remaining five, a last radix 3, and last of
+// all a radix-67 stage (the prime factor of the paper's 128,640 x 85,760
+// grid; see stage_prime).  (Radix 25 would save more stages, but 25 points
+// per item plus the prefetched inputs overflow the 128 registers a thread
+// has at this occupancy.)
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 __host__ __device__ constexpr bool is_pow2c(int v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -301,17 +343,20 @@ __host__ __device__ constexpr int n15(int L) {
 __host__ __device__ constexpr int n9(int L) { return (count_factor(L, 3) - n15(L)) / 2; }
 __host__ __device__ constexpr int n5(int L) { return count_factor(L, 5) - n15(L); }
 __host__ __device__ constexpr int n3(int L) { return (count_factor(L, 3) - n15(L)) % 2; }
+constexpr int kP = 67;  // the prime radix
+__host__ __device__ constexpr int n67(int L) { return count_factor(L, kP); }
 
 __host__ __device__ constexpr int num_stages(int L) {
-  return L <= 1 ? 1 : num_stages_p2(pow2_part(L)) + n15(L) + n9(L) + n5(L) + n3(L);
+  return L <= 1 ? 1 : num_stages_p2(pow2_part(L)) + n15(L) + n9(L) + n5(L) + n3(L) + n67(L);
 }
 
 // radix of odd-factor stage s (s counted from the first odd stage)
 __host__ __device__ constexpr int odd_radix(int L, int s) {
-  return s < n15(L)                     ? 15
-         : s < n15(L) + n9(L)           ? 9
-         : s < n15(L) + n9(L) + n5(L)   ? 5
-                                        : 3;
+  return s < n15(L)                         ? 15
+         : s < n15(L) + n9(L)               ? 9
+         : s < n15(L) + n9(L) + n5(L)       ? 5
+         : s < n15(L) + n9(L) + n5(L) + n3(L) ? 3
+                                            : kP;
 }
 
 __host__ __device__ constexpr int fwd_radix(int L, int s) {
@@ -369,6 +414,134 @@ struct LastRegs {
   static constexpr int PER = StageShape<G, R>::PER;
 };
 
+// ---------------------------------------------------------------------------
+// Radix-67 Stockham stage.  67 points per item do not fit in registers, so
+// the stage works through the tile in LDS, in place:
+//  1. fold: one thread per item reads v_t (after the stage twiddles) and
+//     writes v_t + v_{67-t} to slot t and v_t - v_{67-t} to slot 67 - t,
+//     t = 1..33 (slot 0 keeps v_0);
+//  2. three threads per item each form 11 output pairs from the folded
+//     values, with X_k, X_{67-k} = v_0 + sum_t s_t cos(2 pi t k / 67)
+//     -/+ i sum_t d_t sin(2 pi t k / 67) (forward sign; the symmetric form of
+//     the direct DFT, 2 real multiply-adds per input pair and output), the
+//     constants folded in at compile time; the share rb = 0, 1, 2 is uniform
+//     across a wavefront so that the three code paths do not diverge;
+//  3. the outputs go to the stage's Stockham positions, in LDS or through the
+//     store functor.
+// Inputs come from LDS or the load functor, never from registers, and
+// outputs never go to registers.
+// ---------------------------------------------------------------------------
+constexpr int kPH = (kP - 1) / 2;  // folded input pairs
+constexpr int kPB = 11;            // output pairs per thread (kPH / 3)
+static_assert(3 * kPB == kPH, "three output shares");
+
+template <class G, int RB, bool INV>
+DEV void prime_outputs(const float2 *lds, const int e0, float2 (&o)[2 * kPB + 1]) {
+  constexpr int STEP = (G::L / kP) * G::SJ;
+  constexpr int K0 = 1 + kPB * RB;
+  const float2 x0 = lds[e0];
+  float2 a[kPB], q[kPB];
+  float2 sum = x0;
+#pragma unroll
+  for (int i = 0; i < kPB; ++i) {
+    a[i] = x0;
+    q[i] = make_float2(0.f, 0.f);
+  }
+#pragma unroll
+  for (int t = 1; t <= kPH; ++t) {
+    const float2 sv = lds[e0 + t * STEP], dv = lds[e0 + (kP - t) * STEP];
+    if constexpr (RB == 0) sum = cadd(sum, sv);
+#pragma unroll
+    for (int i = 0; i < kPB; ++i) {
+      const int e = (t * (K0 + i)) % kP;
+      const float c = UnitRoots<kP>::c[e], sn = UnitRoots<kP>::s[e];
+      a[i].x += sv.x * c;
+      a[i].y += sv.y * c;
+      q[i].x += dv.x * sn;
+      q[i].y += dv.y * sn;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kPB; ++i) {
+    const float2 iq = INV ? mul_pi(q[i]) : mul_mi(q[i]);
+    o[2 * i] = cadd(a[i], iq);      // X_{K0 + i}
+    o[2 * i + 1] = csub(a[i], iq);  // X_{67 - K0 - i}
+  }
+  o[2 * kPB] = sum;                 // X_0 (share 0)
+}
+
+template <class G, bool INV, bool FIRST, bool LAST, int NS, int TWMUL, int SRC, int SNK,
+          class LoadF, class StoreF, class Hook>
+DEV void stage_prime(float2 *lds, const float2 *twl, const LoadF &ld, const StoreF &st,
+                     const Hook &hook, const int tid, const int nb_act) {
+  static_assert(SRC != SRC_REG && SNK != SNK_REG,
+                "a radix-67 stage reads and writes LDS or functors, not registers");
+  constexpr int LR = G::L / kP, ITEMS = LR * G::NB;
+  auto at = [](int j, int b) { return j * G::SJ + b * G::SB; };
+  // 1. fold, one thread per item, in place
+  for (int it = tid; it < ITEMS; it += G::T) {
+    int j, b;
+    decode_item<G, kP>(it, j, b);
+    if (b >= nb_act) continue;
+    const int k = FIRST ? 0 : (is_pow2c(NS) ? j & (NS - 1) : (int)((unsigned)j % NS));
+    auto in = [&](int t) {
+      float2 x;
+      if constexpr (SRC == SRC_FN) x = ld(j + t * LR, b);
+      else x = lds[at(j + t * LR, b)];
+      if constexpr (!FIRST) {
+        const float2 w = twl[(t * k) * TWMUL];
+        x = INV ? cmulc(x, w) : cmul(x, w);
+      }
+      return x;
+    };
+    if constexpr (SRC == SRC_FN) lds[at(j, b)] = ld(j, b);
+#pragma unroll 3
+    for (int t = 1; t <= kPH; ++t) {
+      const float2 u = in(t), w = in(kP - t);
+      lds[at(j + t * LR, b)] = cadd(u, w);
+      lds[at(j + (kP - t) * LR, b)] = csub(u, w);
+    }
+  }
+  if constexpr (FIRST) hook();
+  __syncthreads();
+  // 2. outputs: wavefront w takes share w / IW of items (w % IW) * 64 + lane
+  constexpr int IW = (ITEMS + 63) / 64;
+  static_assert(3 * IW * 64 <= G::T, "one output share per thread");
+  const int wv = tid >> 6, rb = wv / IW, it = (wv % IW) * 64 + (tid & 63);
+  int j = 0, b = 0;
+  bool act = rb < 3 && it < ITEMS;
+  if (act) {
+    decode_item<G, kP>(it, j, b);
+    act = b < nb_act;
+  }
+  float2 o[2 * kPB + 1];
+  if (act) {
+    const int e0 = at(j, b);
+    if (rb == 0) prime_outputs<G, 0, INV>(lds, e0, o);
+    else if (rb == 1) prime_outputs<G, 1, INV>(lds, e0, o);
+    else prime_outputs<G, 2, INV>(lds, e0, o);
+  }
+  // 3. output t of item (j, b) goes to (j - k) * 67 + k + t * NS, k = j mod NS
+  constexpr bool TO_LDS = !LAST || SNK == SNK_LDS;
+  if constexpr (TO_LDS) __syncthreads();  // every fold slot has been read
+  if (act) {
+    const int k = is_pow2c(NS) ? j & (NS - 1) : (int)((unsigned)j % NS);
+    const int base = (j - k) * kP + k;
+    auto put = [&](int t, float2 val) {
+      if constexpr (TO_LDS) lds[at(base + t * NS, b)] = val;
+      else st(base + t * NS, b, val);
+    };
+    const int k0 = 1 + kPB * rb;
+#pragma unroll
+    for (int i = 0; i < kPB; ++i) {
+      put(k0 + i, o[2 * i]);
+      put(kP - k0 - i, o[2 * i + 1]);
+    }
+    if (rb == 0) put(0, o[2 * kPB]);
+  }
+  if constexpr (TO_LDS) __syncthreads();
+}
+
 // One Stockham stage S of the L-point DFT along j for every b, followed by the
 // remaining stages.  The first stage reads from SRC (LDS, a load functor
 // ld(j, b), or the register block rin), every later stage from LDS.  The last
@@ -389,6 +562,11 @@ DEV void stages(float2 *lds, const float2 *twl, const LoadF &ld, const StoreF &s
   constexpr int LR = SS::LR, PER = SS::PER, ITEMS = SS::ITEMS;
   static_assert(NS * R <= THI, "twiddle table too small");
   constexpr int TWMUL = THI / (NS * R);  // omega_{NS R}^e = twl[e * TWMUL]
+  if constexpr (R == kP) {
+    stage_prime<G, INV, FIRST, LAST, NS, TWMUL, SRC, SNK>(lds, twl, ld, st, hook, tid, nb_act);
+    if constexpr (!LAST)
+      stages<G, INV, REV, S + 1, SRC_LDS, SNK, THI>(lds, twl, ld, st, hook, rin, rout, tid, nb_act);
+  } else {
   float2 v[PER][R];
   // an item is live if it exists and its batch column is below nb_act (the
   // columns at or beyond nb_act are known to be zero, or are not needed)
@@ -472,6 +650,7 @@ DEV void stages(float2 *lds, const float2 *twl, const LoadF &ld, const StoreF &s
     __syncthreads();
     stages<G, INV, REV, S + 1, SRC_LDS, SNK, THI>(lds, twl, ld, st, hook, rin, rout, tid, nb_act);
   }
+  }
 }
 
 struct NoHook {
@@ -529,10 +708,11 @@ struct NoStore {
 // A' hold up to 16384 (one block per CU) so that every row run they move is a
 // whole 128-byte line.
 //
-// Plan id PID < kNp2Base: M = 2^PID.  PID = kNp2Base + i: the i-th grid of
-// np2_plan, M = 2^a 3^b 5^c with a hand-chosen digit split (AX, BX, AY, BY):
-// BX a power of two >= 16, every tile within the limits above, and every
-// digit length a product of the radices 16/8/4/2, 5 and 3.
+// Plan id PID < kTabBase: the square grid M = 2^PID.  PID = kTabBase + i:
+// the i-th grid of table_plan, My x Mx with Mx = AX * BX and My = AY * BY
+// from a hand-chosen digit split: BX a power of two >= 16, every tile within
+// the limits above, and every digit length a product of the radices
+// 16/8/4/2, 3, 5 and 67.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 __host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
@@ -548,20 +728,27 @@ __host__ __device__ constexpr int threads_for(int pts) {
   return round64(cmin(512, cmax(64, pts / 16)));
 }
 
-struct Np2Plan {
-  int m, ax, bx, ay, by;
+struct TablePlan {
+  int ax, bx, ay, by;  // Mx = ax * bx columns, My = ay * by rows
 };
-constexpr int kNp2Base = 100;
-constexpr int kNumNp2 = 7;
-__host__ __device__ constexpr Np2Plan np2_plan(int i) {
-  return i == 0   ? Np2Plan{240, 15, 16, 15, 16}
-         : i == 1 ? Np2Plan{720, 45, 16, 45, 16}
-         : i == 2 ? Np2Plan{1440, 45, 32, 45, 32}
-         : i == 3 ? Np2Plan{3072, 48, 64, 48, 64}
-         : i == 4 ? Np2Plan{3600, 225, 16, 15, 240}
-         : i == 5 ? Np2Plan{28800, 450, 64, 120, 240}   // 2^7 3^2 5^2
-         : i == 6 ? Np2Plan{40000, 625, 64, 100, 400}   // 2^6 5^4
-                  : Np2Plan{0, 0, 0, 0, 0};
+constexpr int kTabBase = 100;
+constexpr int kNumTab = 14;
+__host__ __device__ constexpr TablePlan table_plan(int i) {
+  return i == 0    ? TablePlan{15, 16, 15, 16}        // 240^2
+         : i == 1  ? TablePlan{45, 16, 45, 16}        // 720^2
+         : i == 2  ? TablePlan{45, 32, 45, 32}        // 1440^2
+         : i == 3  ? TablePlan{48, 64, 48, 64}        // 3072^2
+         : i == 4  ? TablePlan{225, 16, 15, 240}      // 3600^2
+         : i == 5  ? TablePlan{450, 64, 120, 240}     // 28800^2, 2^7 3^2 5^2
+         : i == 6  ? TablePlan{625, 64, 100, 400}     // 40000^2, 2^6 5^4
+         : i == 7  ? TablePlan{134, 16, 16, 134}      // 2144^2, 2^5 67
+         : i == 8  ? TablePlan{15, 16, 45, 16}        // 720 rows x 240 columns
+         : i == 9  ? TablePlan{128, 16, 16, 32}       // 512 x 2048
+         : i == 10 ? TablePlan{134, 16, 15, 16}       // 240 x 2144
+         : i == 11 ? TablePlan{15, 16, 16, 335}       // 5360 x 240
+         : i == 12 ? TablePlan{670, 16, 16, 1005}     // 16080 x 10720
+         : i == 13 ? TablePlan{670, 128, 128, 1005}   // 128640 x 85760: 2^7 3 5 67 x 2^8 5 67
+                   : TablePlan{0, 0, 0, 0};
 }
 
 // Two 512-thread blocks per CU = 4 waves per SIMD: caps registers at 128.
@@ -569,16 +756,17 @@ __host__ __device__ constexpr Np2Plan np2_plan(int i) {
 
 template <int PID>
 struct Plan {
-  static constexpr bool POW2 = PID < kNp2Base;
-  static constexpr Np2Plan NP = np2_plan(POW2 ? -1 : PID - kNp2Base);
-  static constexpr int M = POW2 ? 1 << PID : NP.m;
-  static constexpr size_t PITCH = (size_t)M + kRowPad;  // workspace row pitch
-  static constexpr int BX = POW2 ? 1 << plan_bx(PID) : NP.bx;
-  static constexpr int AX = M / BX;
-  static constexpr int AY = POW2 ? 1 << plan_ay(PID) : NP.ay;
-  static constexpr int BY = M / AY;
+  static constexpr bool POW2 = PID < kTabBase;  // square power-of-two grid
+  static constexpr TablePlan TP = table_plan(POW2 ? -1 : PID - kTabBase);
+  static constexpr int MX = POW2 ? 1 << PID : TP.ax * TP.bx;  // columns
+  static constexpr int MY = POW2 ? 1 << PID : TP.ay * TP.by;  // rows
+  static constexpr size_t PITCH = (size_t)MX + kRowPad;  // workspace row pitch
+  static constexpr int BX = POW2 ? 1 << plan_bx(PID) : TP.bx;
+  static constexpr int AX = MX / BX;
+  static constexpr int AY = POW2 ? 1 << plan_ay(PID) : TP.ay;
+  static constexpr int BY = MY / AY;
   static constexpr int RA = cmin(16, BX);  // contiguous run in passes A / A': a 128-byte line
-  static constexpr int RC = cmin(16, M);   // contiguous run in pass C
+  static constexpr int RC = cmin(16, MX);  // contiguous run in pass C
   // A / A' tiles (up to 1024 x 16 points, 128 KiB of LDS) run one block of
   // up to 1024 threads per CU
   // (other M: about 8 points per thread, since their mixed-radix stage
@@ -590,21 +778,33 @@ struct Plan {
                             : BY * RC > 8192 ? 1024 : threads_for(BY * RC);
   // Twiddles in LDS: omega_M^q = HI[q / S] * LO[q % S] with HI[i] = omega_M^(i S)
   // (= omega_THI^i) and LO[i] = omega_M^i.  Power-of-two M: THI = min(M, 1024),
-  // which also serves every inner DFT length.  Other M: THI = AX (S = BX), the
-  // inner table of passes A and A'; passes B, B' and C keep their own.
-  static constexpr int THI = POW2 ? (M < 1024 ? M : 1024) : AX;
-  static constexpr int S = M / THI;
-  static constexpr int LOGS = ilog2c(S);
-  static_assert(AX * BX == M && AY * BY == M, "digit split");
-  static_assert(is_pow2c(BX) && BX % RA == 0 && M % RC == 0, "runs");
+  // which also serves every inner DFT length.  Table grids: THI = AX (S = BX),
+  // the inner table of passes A and A'; passes B, B' and C keep their own.
+  static constexpr int THI = POW2 ? (MX < 1024 ? MX : 1024) : AX;
+  static constexpr int S = MX / THI;
+  static_assert(AX * BX == MX && AY * BY == MY, "digit split");
+  static_assert(MX % 2 == 0 && MY % 2 == 0, "even axes (signed frequency split at M / 2)");
+  static_assert(is_pow2c(BX) && BX % RA == 0 && MX % RC == 0, "runs");
   static_assert(AX * RA <= 16384 && BX * AY <= 16384 && BY * RC <= 16384, "tile sizes");
   static_assert(AX <= 1024 && BX <= 1024 && AY <= 1024 && BY <= 1024, "digit lengths");
 };
 
-template <int PID>
+// Four-step twiddles of one axis (x: passes A and A'; y: passes B and B').
+// The y axis shares the x tables on a square grid; on a rectangular one it
+// has its own, HI over AY and LO over BY (q = yb * kya < My).
+template <int PID, bool Y>
+struct TwAxis {
+  using P = Plan<PID>;
+  static constexpr bool OWN = Y && P::MX != P::MY;
+  static constexpr int M = Y ? P::MY : P::MX;
+  static constexpr int THI = OWN ? P::AY : P::THI;
+  static constexpr int S = M / THI;
+};
+
+template <int PID, bool Y = false>
 struct TwLds {
-  float2 hi[Plan<PID>::THI];
-  float2 lo[Plan<PID>::S];
+  float2 hi[TwAxis<PID, Y>::THI];
+  float2 lo[TwAxis<PID, Y>::S];
 };
 
 // exp(-2 pi i num / den), 0 <= num < den, formed in FP64 and rounded once.
@@ -615,16 +815,17 @@ DEV float2 omega_fp64(int num, int den) {
 }
 
 // This plan's twiddles in LDS: from the FP64-generated global table
-// (power-of-two M), or generated in FP64 (other M).
-template <int PID, int T>
-DEV void tw_fill(TwLds<PID> &t, const float2 *__restrict__ g) {
+// (power-of-two M), or generated in FP64 (table grids).
+template <int PID, int T, bool Y = false>
+DEV void tw_fill(TwLds<PID, Y> &t, const float2 *__restrict__ g) {
   using P = Plan<PID>;
+  using A = TwAxis<PID, Y>;
   if constexpr (P::POW2) {
-    for (int i = threadIdx.x; i < P::THI; i += T) t.hi[i] = g[(i * P::S) << (kTwLog - PID)];
-    for (int i = threadIdx.x; i < P::S; i += T) t.lo[i] = g[i << (kTwLog - PID)];
+    for (int i = threadIdx.x; i < A::THI; i += T) t.hi[i] = g[(i * A::S) << (kTwLog - PID)];
+    for (int i = threadIdx.x; i < A::S; i += T) t.lo[i] = g[i << (kTwLog - PID)];
   } else {
-    for (int i = threadIdx.x; i < P::THI; i += T) t.hi[i] = omega_fp64(i * P::S, P::M);
-    for (int i = threadIdx.x; i < P::S; i += T) t.lo[i] = omega_fp64(i, P::M);
+    for (int i = threadIdx.x; i < A::THI; i += T) t.hi[i] = omega_fp64(i * A::S, A::M);
+    for (int i = threadIdx.x; i < A::S; i += T) t.lo[i] = omega_fp64(i, A::M);
   }
 }
 
@@ -634,15 +835,15 @@ DEV void omega_fill(float2 *t) {
   for (int i = threadIdx.x; i < L; i += T) t[i] = omega_fp64(i, L);
 }
 
-// omega_M^q (forward sign), q >= 0.
-template <int PID>
-DEV float2 tw_q(const TwLds<PID> &t, int q) {
-  using P = Plan<PID>;
-  const unsigned u = (unsigned)q % (unsigned)P::M;
-  if constexpr (P::S == 1) {
+// omega_M^q (forward sign) of the axis, q >= 0.
+template <int PID, bool Y = false>
+DEV float2 tw_q(const TwLds<PID, Y> &t, int q) {
+  using A = TwAxis<PID, Y>;
+  const unsigned u = (unsigned)q % (unsigned)A::M;
+  if constexpr (A::S == 1) {
     return t.hi[u];
   } else {
-    return cmul(t.hi[u / P::S], t.lo[u % P::S]);
+    return cmul(t.hi[u / A::S], t.lo[u % A::S]);
   }
 }
 
@@ -702,7 +903,7 @@ DEV double sqrt_unit(double q) {
   return fma(g, e, g);
 }
 
-// Per-axis frequency data of DFT bin k of M: f = k_signed / (M dx), the
+// Per-axis frequency data of DFT bin k of an M-point axis: f = k_signed / (M dx), the
 // square (lambda f)^2 with each product rounded once in FP64 (no
 // contraction), as the evanescent test needs, and whether |f| is inside the
 // band limit (always, unless DOP_BANDLIMIT).
@@ -710,12 +911,12 @@ struct AxisFreq {
   double a2;
   bool inband;
 };
-DEV AxisFreq axis_freq(int k, int m, const KParams &p) {
+DEV AxisFreq axis_freq(int k, int m, double inv_md, double flim, const KParams &p) {
 #pragma clang fp contract(off)
   const int ks = k < (m >> 1) ? k : k - m;
-  const double f = (double)ks * p.inv_mdx;
+  const double f = (double)ks * inv_md;
   const double a = p.lam * f;
-  return AxisFreq{a * a, fabs(f) < p.flim};
+  return AxisFreq{a * a, fabs(f) < flim};
 }
 
 // (lambda f)^2 of one axis with the band limit folded in: a frequency outside
@@ -860,11 +1061,11 @@ DOP_KERNEL(Plan<PID>::TB) void k_pass_b_fwd(KParams p) {
   constexpr int HB = BX / 2;  // 16-byte pairs per row segment
   constexpr int PF = (AY * HB + T - 1) / T;  // pairs each thread moves per tile
   __shared__ float2 lds[AY * SR];
-  __shared__ TwLds<PID> tw;
+  __shared__ TwLds<PID, true> tw;  // y four-step twiddles omega_My
   __shared__ float2 rowtw[AY];
   // inner twiddles: the shared power-of-two table, else tables of their own
   __shared__ float2 wbx[P::POW2 ? 1 : BX], way[P::POW2 ? 1 : AY];
-  tw_fill<PID, T>(tw, p.tw);
+  tw_fill<PID, T, true>(tw, p.tw);
   if constexpr (!P::POW2) {
     omega_fill<BX, T>(wbx);
     omega_fill<AY, T>(way);
@@ -902,7 +1103,7 @@ DOP_KERNEL(Plan<PID>::TB) void k_pass_b_fwd(KParams p) {
     const size_t col0 = (size_t)BX * kxa;
     const int nz = nzrows(yb);
     __syncthreads();
-    for (int r = tid; r < AY; r += T) rowtw[r] = tw_q<PID>(tw, yb * r);  // omega_M^(yb kya)
+    for (int r = tid; r < AY; r += T) rowtw[r] = tw_q<PID, true>(tw, yb * r);  // omega_My^(yb kya)
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
       const int e = tid + i * T, ya = e / HB, c = e % HB;
@@ -933,26 +1134,36 @@ DOP_KERNEL(Plan<PID>::TB) void k_pass_b_fwd(KParams p) {
 template <int PID>
 DOP_KERNEL(Plan<PID>::TC) void k_pass_c(KParams p) {
   using P = Plan<PID>;
-  constexpr int AX = P::AX, BX = P::BX, AY = P::AY, BY = P::BY, M = P::M, RC = P::RC, T = P::TC;
+  constexpr int AX = P::AX, BX = P::BX, AY = P::AY, BY = P::BY, RC = P::RC, T = P::TC;
   using G = Geo<BY, RC, RC + 1, 1, T, false>;
   using FS = FirstStage<G>;
+  // A radix-67 stage cannot hand its outputs over in registers: with one, the
+  // forward DFT ends in LDS (natural order) and the inverse DFT reads it
+  // through a load functor that applies H.
+  constexpr bool VIA_LDS = n67(BY) > 0;
   static_assert((size_t)BY * P::PITCH < (1ull << 31), "tile offsets are 32-bit");
   __shared__ float2 lds[BY * (RC + 1)];
   // only BY-point DFTs run here: their twiddles omega_BY^i, i < BY
   __shared__ float2 twc[BY];
-  // a2_eff of the tile's BY frequency rows
+  // a2_eff of the tile's BY frequency rows (and, via LDS, of its RC columns)
   __shared__ double a2row[BY];
+  __shared__ double a2col[VIA_LDS ? RC : 1];
   if constexpr (P::POW2) {
     for (int i = threadIdx.x; i < BY; i += T) twc[i] = p.tw[i << (kTwLog - ilog2c(BY))];
   } else {
     omega_fill<BY, T>(twc);
   }
-  constexpr int RUNS = M / RC;
+  constexpr int RUNS = P::MX / RC;
   constexpr int NT = AY * RUNS;
-  using LR_ = LastRegs<G, false>;
   auto tile_base = [&](int pt) {
     const int tile = xcd_tile(pt, NT);
     return p.ws + (size_t)(BY * (tile / RUNS)) * P::PITCH + (tile % RUNS) * RC;
+  };
+  // frequency-x data of padded column px (spectrum position BX kxa + kxb
+  // holds kx = kxa + AX kxb)
+  auto col_a2 = [&](int px) {
+    const int kx = (px / BX) + AX * (px % BX);
+    return a2_eff(axis_freq(kx, P::MX, p.inv_mdx, p.flim_x, p));
   };
   // one tile's first-stage inputs, loaded one tile ahead
   float2 pre[FS::PER][FS::R];
@@ -980,7 +1191,10 @@ DOP_KERNEL(Plan<PID>::TC) void k_pass_c(KParams p) {
     __syncthreads();
     // frequency rows of this tile: position kyb holds ky = kya + AY kyb; read
     // after the forward DFT, whose stage barriers order this write before them
-    for (int r = tid; r < BY; r += T) a2row[r] = a2_eff(axis_freq(kya + AY * r, M, p));
+    for (int r = tid; r < BY; r += T)
+      a2row[r] = a2_eff(axis_freq(kya + AY * r, P::MY, p.inv_mdy, p.flim_y, p));
+    if constexpr (VIA_LDS)
+      for (int c = tid; c < RC; c += T) a2col[c] = col_a2(px0 + c);
     float2 v[FS::PER][FS::R];
 #pragma unroll
     for (int i = 0; i < FS::PER; ++i)
@@ -989,32 +1203,41 @@ DOP_KERNEL(Plan<PID>::TC) void k_pass_c(KParams p) {
     auto hook = [&]() {
       if (pt + (int)gridDim.x < NT) fetch(pt + gridDim.x, tid);
     };
-    float2 regs[LR_::PER][LR_::R];
-    dft_tile_hooked<G, false, false, SRC_REG, SNK_REG, BY>(lds, twc, NoLoad{}, NoStore{}, hook, v,
-                                                          regs, tid);
-    {
-      constexpr int R = LR_::R;
-      constexpr int LRn = BY / R;
-      using SS = StageShape<G, R>;
-#pragma unroll
-      for (int i = 0; i < LR_::PER; ++i) {
-        const int it = tid + i * T;
-        if (SS::EXACT || it < SS::ITEMS) {
-          int j, b;
-          decode_item<G, R>(it, j, b);
-          const int px = px0 + b;
-          const int kx = (px / BX) + AX * (px % BX);
-          const double a2x = a2_eff(axis_freq(kx, M, p));
-#pragma unroll
-          for (int t = 0; t < R; ++t)
-            regs[i][t] = cmul(regs[i][t], transfer(a2row[j + t * LRn], a2x, p));
-        }
-      }
-    }
     auto st = [&](int yb, int b, float2 w) {
       *at_byte(base, ((unsigned)yb * (unsigned)P::PITCH + b) * 8u) = w;
     };
-    dft_tile<G, true, true, SRC_REG, SNK_FN, BY>(lds, twc, NoLoad{}, st, regs, tid);
+    if constexpr (VIA_LDS) {
+      float2 dummy[1][1];
+      dft_tile_hooked<G, false, false, SRC_REG, SNK_LDS, BY>(lds, twc, NoLoad{}, NoStore{}, hook,
+                                                            v, dummy, tid);
+      auto ld_h = [&](int kyb, int b) {
+        return cmul(lds[kyb * (RC + 1) + b], transfer(a2row[kyb], a2col[b], p));
+      };
+      dft_tile<G, true, true, SRC_FN, SNK_FN, BY>(lds, twc, ld_h, st, dummy, tid);
+    } else {
+      using LR_ = LastRegs<G, false>;
+      float2 regs[LR_::PER][LR_::R];
+      dft_tile_hooked<G, false, false, SRC_REG, SNK_REG, BY>(lds, twc, NoLoad{}, NoStore{}, hook,
+                                                            v, regs, tid);
+      {
+        constexpr int R = LR_::R;
+        constexpr int LRn = BY / R;
+        using SS = StageShape<G, R>;
+#pragma unroll
+        for (int i = 0; i < LR_::PER; ++i) {
+          const int it = tid + i * T;
+          if (SS::EXACT || it < SS::ITEMS) {
+            int j, b;
+            decode_item<G, R>(it, j, b);
+            const double a2x = col_a2(px0 + b);
+#pragma unroll
+            for (int t = 0; t < R; ++t)
+              regs[i][t] = cmul(regs[i][t], transfer(a2row[j + t * LRn], a2x, p));
+          }
+        }
+      }
+      dft_tile<G, true, true, SRC_REG, SNK_FN, BY>(lds, twc, NoLoad{}, st, regs, tid);
+    }
   }
 }
 
@@ -1030,10 +1253,10 @@ DOP_KERNEL(Plan<PID>::TB) void k_pass_b_inv(KParams p) {
   constexpr int HB = BX / 2;
   constexpr int PF = (AY * HB + T - 1) / T;
   __shared__ float2 lds[AY * SR];
-  __shared__ TwLds<PID> tw;
+  __shared__ TwLds<PID, true> tw;
   __shared__ float2 rowtw[AY];
   __shared__ float2 wbx[P::POW2 ? 1 : BX], way[P::POW2 ? 1 : AY];
-  tw_fill<PID, T>(tw, p.tw);
+  tw_fill<PID, T, true>(tw, p.tw);
   if constexpr (!P::POW2) {
     omega_fill<BX, T>(wbx);
     omega_fill<AY, T>(way);
@@ -1064,7 +1287,7 @@ DOP_KERNEL(Plan<PID>::TB) void k_pass_b_inv(KParams p) {
     // only the rows ya with BY*ya + yb < nrows_out are needed
     const int nz = p.nrows_out > yb ? cmin(AY, (p.nrows_out - yb + BY - 1) / BY) : 0;
     __syncthreads();
-    for (int r = tid; r < AY; r += T) rowtw[r] = tw_q<PID>(tw, yb * r);
+    for (int r = tid; r < AY; r += T) rowtw[r] = tw_q<PID, true>(tw, yb * r);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
@@ -1096,12 +1319,16 @@ DOP_KERNEL(Plan<PID>::TB) void k_pass_b_inv(KParams p) {
 template <int PID, int OUTM>
 DOP_KERNEL(Plan<PID>::TA) void k_pass_a_inv(KParams p) {
   using P = Plan<PID>;
-  constexpr int AX = P::AX, BX = P::BX, RA = P::RA, M = P::M, T = P::TA;
+  constexpr int AX = P::AX, BX = P::BX, RA = P::RA, MX = P::MX, MY = P::MY, T = P::TA;
   using G = Geo<AX, RA, RA, 1, T, false>;
   using FS = FirstStage<G>;
+  // A radix-67 last stage writes through a store functor that does the
+  // output stage; otherwise the last stage's registers are finished here.
+  constexpr bool VIA_FN = n67(AX) > 0;
   using LS = LastRegs<G, false>;
   constexpr int LRL = AX / LS::R;
   using SSL = StageShape<G, LS::R>;
+  constexpr int APER = VIA_FN ? 1 : LS::PER, AR = VIA_FN ? 1 : LS::R;
   __shared__ float2 lds[AX * RA];
   __shared__ TwLds<PID> tw;
   tw_fill<PID, T>(tw, p.tw);
@@ -1128,11 +1355,28 @@ DOP_KERNEL(Plan<PID>::TA) void k_pass_a_inv(KParams p) {
   auto out_index = [&](int y, int xb0, int xa, int b) -> long long {
     const int x = BX * xa + xb0 + b;
     if (p.full) {
-      const int ys = y + p.p0, xs = x + p.p0;  // both < 2M
-      const int yo = ys >= M ? ys - M : ys, xo = xs >= M ? xs - M : xs;
-      return (long long)yo * M + xo;
+      const int ys = y + p.p0y, xs = x + p.p0x;  // ys < 2 My, xs < 2 Mx
+      const int yo = ys >= MY ? ys - MY : ys, xo = xs >= MX ? xs - MX : xs;
+      return (long long)yo * MX + xo;
     }
     return x < n ? (long long)y * n + x : -1;
+  };
+  // output stage of one element: w is My Mx U (the inverse DFT's 1/(My Mx)
+  // is applied here), accv the accumulator value it adds to
+  auto finish = [&](int y, int x, long long idx, float2 w, float accv) {
+    if constexpr (OUTM == OUT_PSF) {
+      p.psf[idx] = accv + p.wk_m4 * (w.x * w.x + w.y * w.y);
+      if (p.saved_out) p.saved_out[idx] = cscale(w, p.inv_m2);
+    } else if constexpr (OUTM == OUT_FIELD) {
+      p.u_out[idx] = cscale(w, p.inv_m2);
+    } else {
+      // crop only: x < n here
+      float2 e = doe_phase(p.h[(size_t)(y >> p.up_log2) * p.nh + (x >> p.up_log2)],
+                           p.phase_turns);
+      if (p.amp) e = cscale(e, p.amp[idx]);
+      // c_k Im(g_E conj(E)), g_E = w / (My Mx)
+      p.grad_h[idx] = accv + p.ck_m2 * (w.y * e.x - w.x * e.y);
+    }
   };
   constexpr int CH = RUNS < 4 ? RUNS : 4;
   const ChunkSeq<CH> seq(ntiles);
@@ -1161,52 +1405,52 @@ DOP_KERNEL(Plan<PID>::TA) void k_pass_a_inv(KParams p) {
     // to, then start the next tile's loads.  Loads complete in issue order, so
     // the accumulator reads go first: waiting for them at the end of this
     // tile must not also wait for the prefetch.
-    float acc[LS::PER][LS::R];
+    float acc[APER][AR];
     auto hook = [&]() {
+      if constexpr (!VIA_FN) {
 #pragma unroll
-      for (int i = 0; i < LS::PER; ++i) {
-        const int it = tid + i * T;
-        int j = 0, b = 0;
-        if (SSL::EXACT || it < SSL::ITEMS) decode_item<G, LS::R>(it, j, b);
+        for (int i = 0; i < LS::PER; ++i) {
+          const int it = tid + i * T;
+          int j = 0, b = 0;
+          if (SSL::EXACT || it < SSL::ITEMS) decode_item<G, LS::R>(it, j, b);
 #pragma unroll
-        for (int t = 0; t < LS::R; ++t) {
-          acc[i][t] = 0.f;
-          if (accumulate && (SSL::EXACT || it < SSL::ITEMS)) {
-            const long long idx = out_index(y, xb0, j + t * LRL, b);
-            if (idx >= 0) acc[i][t] = (OUTM == OUT_PSF) ? p.psf[idx] : p.grad_h[idx];
+          for (int t = 0; t < LS::R; ++t) {
+            acc[i][t] = 0.f;
+            if (accumulate && (SSL::EXACT || it < SSL::ITEMS)) {
+              const long long idx = out_index(y, xb0, j + t * LRL, b);
+              if (idx >= 0) acc[i][t] = (OUTM == OUT_PSF) ? p.psf[idx] : p.grad_h[idx];
+            }
           }
         }
       }
       const int nt = seq.tile(k + 1) >= 0 ? seq.tile(k + 1) : seq.tile(k + 2);
       if (nt >= 0) fetch(nt, tid);
     };
-    float2 u[LS::PER][LS::R];
-    dft_tile_hooked<G, true, false, SRC_REG, SNK_REG, P::THI>(lds, tw.hi, NoLoad{}, NoStore{}, hook,
-                                                             v, u, tid);
+    if constexpr (VIA_FN) {
+      float2 dummy[1][1];
+      auto st = [&](int xa, int b, float2 w) {
+        const long long idx = out_index(y, xb0, xa, b);
+        if (idx < 0) return;
+        const float accv = !accumulate ? 0.f : (OUTM == OUT_PSF) ? p.psf[idx] : p.grad_h[idx];
+        finish(y, BX * xa + xb0 + b, idx, w, accv);
+      };
+      dft_tile_hooked<G, true, false, SRC_REG, SNK_FN, P::THI>(lds, tw.hi, NoLoad{}, st, hook, v,
+                                                              dummy, tid);
+    } else {
+      float2 u[LS::PER][LS::R];
+      dft_tile_hooked<G, true, false, SRC_REG, SNK_REG, P::THI>(lds, tw.hi, NoLoad{}, NoStore{},
+                                                               hook, v, u, tid);
 #pragma unroll
-    for (int i = 0; i < LS::PER; ++i) {
-      const int it = tid + i * T;
-      if (SSL::EXACT || it < SSL::ITEMS) {
-        int j, b;
-        decode_item<G, LS::R>(it, j, b);
+      for (int i = 0; i < LS::PER; ++i) {
+        const int it = tid + i * T;
+        if (SSL::EXACT || it < SSL::ITEMS) {
+          int j, b;
+          decode_item<G, LS::R>(it, j, b);
 #pragma unroll
-        for (int t = 0; t < LS::R; ++t) {
-          const long long idx = out_index(y, xb0, j + t * LRL, b);
-          if (idx < 0) continue;
-          const float2 w = u[i][t];
-          // w is M^2 U: the inverse DFT's 1/M^2 is applied here
-          if constexpr (OUTM == OUT_PSF) {
-            p.psf[idx] = acc[i][t] + p.wk_m4 * (w.x * w.x + w.y * w.y);
-            if (p.saved_out) p.saved_out[idx] = cscale(w, p.inv_m2);
-          } else if constexpr (OUTM == OUT_FIELD) {
-            p.u_out[idx] = cscale(w, p.inv_m2);
-          } else {
-            const int x = BX * (j + t * LRL) + xb0 + b;  // crop only: x < n here
-            float2 e = doe_phase(p.h[(size_t)(y >> p.up_log2) * p.nh + (x >> p.up_log2)],
-                                 p.phase_turns);
-            if (p.amp) e = cscale(e, p.amp[idx]);
-            // c_k Im(g_E conj(E)), g_E = w / M^2
-            p.grad_h[idx] = acc[i][t] + p.ck_m2 * (w.y * e.x - w.x * e.y);
+          for (int t = 0; t < LS::R; ++t) {
+            const long long idx = out_index(y, xb0, j + t * LRL, b);
+            if (idx < 0) continue;
+            finish(y, BX * (j + t * LRL) + xb0 + b, idx, u[i][t], acc[i][t]);
           }
         }
       }
@@ -1229,7 +1473,7 @@ static hipError_t launch_impl(const KParams &p, hipStream_t s, hipEvent_t *ev) {
   };
   const unsigned ga = grid((long long)p.nrows_in * (P::BX / P::RA));
   const unsigned gb = grid((long long)P::AX * P::BY);
-  const unsigned gc = grid((long long)P::AY * (P::M / P::RC));
+  const unsigned gc = grid((long long)P::AY * (P::MX / P::RC));
   const unsigned gai = grid((long long)p.nrows_out * (P::BX / P::RA));
   mark(ev, 0, s);
   if (p.in_mode == IN_PHASE)
@@ -1271,28 +1515,41 @@ hipError_t launch_wavelength(const KParams &p, hipStream_t s, hipEvent_t *ev) {
     case 15: return launch_impl<15>(p, s, ev);
     case 16: return launch_impl<16>(p, s, ev);
     case 17: return launch_impl<17>(p, s, ev);
-    case kNp2Base + 0: return launch_impl<kNp2Base + 0>(p, s, ev);
-    case kNp2Base + 1: return launch_impl<kNp2Base + 1>(p, s, ev);
-    case kNp2Base + 2: return launch_impl<kNp2Base + 2>(p, s, ev);
-    case kNp2Base + 3: return launch_impl<kNp2Base + 3>(p, s, ev);
-    case kNp2Base + 4: return launch_impl<kNp2Base + 4>(p, s, ev);
-    case kNp2Base + 5: return launch_impl<kNp2Base + 5>(p, s, ev);
-    case kNp2Base + 6: return launch_impl<kNp2Base + 6>(p, s, ev);
+    case kTabBase + 0: return launch_impl<kTabBase + 0>(p, s, ev);
+    case kTabBase + 1: return launch_impl<kTabBase + 1>(p, s, ev);
+    case kTabBase + 2: return launch_impl<kTabBase + 2>(p, s, ev);
+    case kTabBase + 3: return launch_impl<kTabBase + 3>(p, s, ev);
+    case kTabBase + 4: return launch_impl<kTabBase + 4>(p, s, ev);
+    case kTabBase + 5: return launch_impl<kTabBase + 5>(p, s, ev);
+    case kTabBase + 6: return launch_impl<kTabBase + 6>(p, s, ev);
+    case kTabBase + 7: return launch_impl<kTabBase + 7>(p, s, ev);
+    case kTabBase + 8: return launch_impl<kTabBase + 8>(p, s, ev);
+    case kTabBase + 9: return launch_impl<kTabBase + 9>(p, s, ev);
+    case kTabBase + 10: return launch_impl<kTabBase + 10>(p, s, ev);
+    case kTabBase + 11: return launch_impl<kTabBase + 11>(p, s, ev);
+    case kTabBase + 12: return launch_impl<kTabBase + 12>(p, s, ev);
+    case kTabBase + 13: return launch_impl<kTabBase + 13>(p, s, ev);
     default: return hipErrorInvalidValue;
   }
 }
-static_assert(kNumNp2 == 7, "one launch case per grid of np2_plan");
+static_assert(kNumTab == 14, "one launch case per grid of table_plan");
 
-int plan_id(int m) {
-  if (m >= 16 && m <= (1 << 17) && is_pow2c(m)) return ilog2c(m);
-  for (int i = 0; i < kNumNp2; ++i)
-    if (np2_plan(i).m == m) return kNp2Base + i;
+int plan_id(int mx, int my) {
+  if (mx == my && mx >= 16 && mx <= (1 << 17) && is_pow2c(mx)) return ilog2c(mx);
+  for (int i = 0; i < kNumTab; ++i) {
+    const TablePlan t = table_plan(i);
+    if (t.ax * t.bx == mx && t.ay * t.by == my) return kTabBase + i;
+  }
   return -1;
 }
 
-int np2_grids(int *out, int max) {
-  for (int i = 0; i < kNumNp2 && i < max; ++i) out[i] = np2_plan(i).m;
-  return kNumNp2;
+int table_grids(int *rows, int *cols, int max) {
+  for (int i = 0; i < kNumTab && i < max; ++i) {
+    const TablePlan t = table_plan(i);
+    rows[i] = t.ay * t.by;
+    cols[i] = t.ax * t.bx;
+  }
+  return kNumTab;
 }
 
 template <int PID>
@@ -1318,13 +1575,20 @@ bool plan_info(int plan, PlanInfo *o) {
     case 15: fill_plan<15>(o); return true;
     case 16: fill_plan<16>(o); return true;
     case 17: fill_plan<17>(o); return true;
-    case kNp2Base + 0: fill_plan<kNp2Base + 0>(o); return true;
-    case kNp2Base + 1: fill_plan<kNp2Base + 1>(o); return true;
-    case kNp2Base + 2: fill_plan<kNp2Base + 2>(o); return true;
-    case kNp2Base + 3: fill_plan<kNp2Base + 3>(o); return true;
-    case kNp2Base + 4: fill_plan<kNp2Base + 4>(o); return true;
-    case kNp2Base + 5: fill_plan<kNp2Base + 5>(o); return true;
-    case kNp2Base + 6: fill_plan<kNp2Base + 6>(o); return true;
+    case kTabBase + 0: fill_plan<kTabBase + 0>(o); return true;
+    case kTabBase + 1: fill_plan<kTabBase + 1>(o); return true;
+    case kTabBase + 2: fill_plan<kTabBase + 2>(o); return true;
+    case kTabBase + 3: fill_plan<kTabBase + 3>(o); return true;
+    case kTabBase + 4: fill_plan<kTabBase + 4>(o); return true;
+    case kTabBase + 5: fill_plan<kTabBase + 5>(o); return true;
+    case kTabBase + 6: fill_plan<kTabBase + 6>(o); return true;
+    case kTabBase + 7: fill_plan<kTabBase + 7>(o); return true;
+    case kTabBase + 8: fill_plan<kTabBase + 8>(o); return true;
+    case kTabBase + 9: fill_plan<kTabBase + 9>(o); return true;
+    case kTabBase + 10: fill_plan<kTabBase + 10>(o); return true;
+    case kTabBase + 11: fill_plan<kTabBase + 11>(o); return true;
+    case kTabBase + 12: fill_plan<kTabBase + 12>(o); return true;
+    case kTabBase + 13: fill_plan<kTabBase + 13>(o); return true;
     default: return false;
   }
 }

@@ -56,15 +56,23 @@ dop_status validate_problem(const dop_problem *prob) {
   if (!prob) return fail(DOP_ERR_INVALID_ARG, "problem is NULL");
   if (prob->n < 1) return fail(DOP_ERR_INVALID_ARG, "n must be >= 1 (got %d)", prob->n);
   if (prob->m < 1) return fail(DOP_ERR_INVALID_ARG, "m must be >= 1 (got %d)", prob->m);
-  if (plan_id(prob->m) < 0) {
-    int g[16];
-    const int ng = np2_grids(g, 16);
+  if (prob->ny < 0) return fail(DOP_ERR_INVALID_ARG, "ny must be >= 0 (got %d)", prob->ny);
+  if (prob->my < 0) return fail(DOP_ERR_INVALID_ARG, "my must be >= 0 (got %d)", prob->my);
+  const int mx = grid_cols(prob), my = grid_rows(prob);
+  if (plan_id(mx, my) < 0) {
+    int gr[32], gc[32];
+    const int ng = table_grids(gr, gc, 32);
     std::string list;
-    for (int i = 0; i < ng && i < 16; ++i) list += (i ? ", " : "") + std::to_string(g[i]);
-    return fail(DOP_ERR_UNSUPPORTED, "m must be a power of two in [%d, %d] or one of %s (got %d)",
-                DOP_MIN_M, DOP_MAX_M, list.c_str(), prob->m);
+    for (int i = 0; i < ng && i < 32; ++i)
+      list += (i ? ", " : "") + (gr[i] == gc[i] ? std::to_string(gc[i]) + "^2"
+                                                : std::to_string(gr[i]) + "x" + std::to_string(gc[i]));
+    return fail(DOP_ERR_UNSUPPORTED,
+                "grid %d rows x %d columns has no plan: square powers of two in [%d, %d] and "
+                "%s (rows x columns)", my, mx, DOP_MIN_M, DOP_MAX_M, list.c_str());
   }
-  if (prob->n > prob->m) return fail(DOP_ERR_INVALID_ARG, "n (%d) exceeds m (%d)", prob->n, prob->m);
+  if (prob->n > mx) return fail(DOP_ERR_INVALID_ARG, "n (%d) exceeds m (%d)", prob->n, mx);
+  if (doe_rows(prob) > my)
+    return fail(DOP_ERR_INVALID_ARG, "ny (%d) exceeds my (%d)", doe_rows(prob), my);
   if (!(prob->dx > 0.0) || !std::isfinite(prob->dx))
     return fail(DOP_ERR_INVALID_ARG, "dx must be finite and > 0");
   if (!std::isfinite(prob->z)) return fail(DOP_ERR_INVALID_ARG, "z must be finite");
@@ -88,9 +96,9 @@ dop_status validate_problem(const dop_problem *prob) {
   if (prob->upsample < 0 || prob->upsample > DOP_MAX_UPSAMPLE || !is_pow2(upsample_factor(prob)))
     return fail(DOP_ERR_UNSUPPORTED, "upsample must be 0, 1, 2, 4, 8 or 16 (got %d)",
                 prob->upsample);
-  if (prob->n % upsample_factor(prob) != 0)
-    return fail(DOP_ERR_INVALID_ARG, "upsample factor %d does not divide n = %d", prob->upsample,
-                prob->n);
+  if (prob->n % upsample_factor(prob) != 0 || doe_rows(prob) % upsample_factor(prob) != 0)
+    return fail(DOP_ERR_INVALID_ARG, "upsample factor %d does not divide n = %d and ny = %d",
+                prob->upsample, prob->n, doe_rows(prob));
   // The phase and transfer arguments are reduced in FP64; beyond ~2^40 turns
   // their fractional part would carry no bits.
   for (int k = 0; k < prob->n_lambda; ++k) {
@@ -101,7 +109,7 @@ dop_status validate_problem(const dop_problem *prob) {
 }
 
 size_t workspace_bytes(const dop_problem *prob) {
-  return (size_t)prob->m * ((size_t)prob->m + kRowPad) * sizeof(float2);
+  return (size_t)grid_rows(prob) * ((size_t)grid_cols(prob) + kRowPad) * sizeof(float2);
 }
 
 // Byte offset of the fine-grid gradient in a DOP_OP_PSF_BACKWARD workspace
@@ -112,13 +120,14 @@ static size_t fine_grad_offset(const dop_problem *prob) {
 
 static size_t workspace_bytes_op(const dop_problem *prob, int op) {
   if (op == DOP_OP_PSF_BACKWARD && upsample_factor(prob) > 1)
-    return fine_grad_offset(prob) + (size_t)prob->n * prob->n * sizeof(float);
+    return fine_grad_offset(prob) + (size_t)doe_rows(prob) * prob->n * sizeof(float);
   return workspace_bytes(prob);
 }
 
 // Band limit of the sampled transfer function (see DOP_BANDLIMIT), formed
 // exactly as 1 / (lambda sqrt(t t + 1)), t = 2 |z| / (M dx), without FMA
-// contraction, so the mask matches a plain FP64 evaluation bin for bin.
+// contraction, so the mask matches a plain FP64 evaluation bin for bin.  m is
+// the length of the axis the limit applies to.
 static double band_limit(double lam, double z, int m, double dx) {
 #pragma clang fp contract(off)
   const double t = 2.0 * std::fabs(z) / ((double)m * dx);
@@ -130,22 +139,25 @@ void fill_common(KParams &kp, const dop_context *ctx, const dop_problem *prob, i
   std::memset(&kp, 0, sizeof(kp));
   kp.ws = static_cast<float2 *>(ws);
   kp.tw = ctx->tw;
+  const int mx = grid_cols(prob), my = grid_rows(prob);
   kp.n = prob->n;
-  kp.m = prob->m;
-  kp.plan = plan_id(prob->m);
-  kp.nrows_in = prob->n;
-  kp.p0 = (prob->m - prob->n) / 2;
+  kp.plan = plan_id(mx, my);
+  kp.nrows_in = doe_rows(prob);
+  kp.p0x = (mx - prob->n) / 2;
+  kp.p0y = (my - doe_rows(prob)) / 2;
   kp.up_log2 = ilog2i(upsample_factor(prob));
   kp.nh = prob->n >> kp.up_log2;
   const double lam = prob->lambda[k];
   kp.lam = lam;
   kp.zl = prob->z / lam;
-  kp.inv_mdx = 1.0 / ((double)prob->m * prob->dx);
-  kp.flim = (prob->flags & DOP_BANDLIMIT) ? band_limit(lam, prob->z, prob->m, prob->dx)
-                                          : HUGE_VAL;
+  kp.inv_mdx = 1.0 / ((double)mx * prob->dx);
+  kp.inv_mdy = 1.0 / ((double)my * prob->dx);
+  const bool bl = (prob->flags & DOP_BANDLIMIT) != 0;
+  kp.flim_x = bl ? band_limit(lam, prob->z, mx, prob->dx) : HUGE_VAL;
+  kp.flim_y = bl ? band_limit(lam, prob->z, my, prob->dx) : HUGE_VAL;
   kp.phase_turns = (prob->n_index[k] - 1.0) / lam;
   const float w = prob->weight ? prob->weight[k] : 1.0f;
-  const double m2 = (double)prob->m * (double)prob->m;
+  const double m2 = (double)mx * (double)my;
   kp.wk_m4 = (float)((double)w / (m2 * m2));
   kp.two_wk = 2.0f * w;
   kp.ck_m2 = (float)(2.0 * M_PI * (prob->n_index[k] - 1.0) / lam / m2);
@@ -190,14 +202,14 @@ dop_status check_ctx_device(const dop_context *ctx) {
 
 dop_status enqueue_psf(const dop_context *ctx, const dop_problem *prob, const float *h,
                        const float *amp, float *psf, void *saved_u, void *ws, hipStream_t stream) {
-  const size_t nn = (size_t)prob->n * prob->n;
+  const size_t nn = (size_t)doe_rows(prob) * prob->n;
   for (int k = 0; k < prob->n_lambda; ++k) {
     KParams kp;
     fill_common(kp, ctx, prob, k, ws);
     kp.in_mode = IN_PHASE;
     kp.out_mode = OUT_PSF;
     kp.full = prob->out_mode == DOP_OUT_FULL;
-    kp.nrows_out = kp.full ? prob->m : prob->n;
+    kp.nrows_out = kp.full ? grid_rows(prob) : doe_rows(prob);
     kp.first = (k == 0);
     kp.h = h;
     kp.amp = amp;
@@ -383,7 +395,7 @@ dop_status dop_propagate(dop_context *ctx, const dop_problem *prob, int k, const
   kp.in_mode = IN_FIELD;
   kp.out_mode = OUT_FIELD;
   kp.full = prob->out_mode == DOP_OUT_FULL;
-  kp.nrows_out = kp.full ? prob->m : prob->n;
+  kp.nrows_out = kp.full ? grid_rows(prob) : doe_rows(prob);
   kp.first = 1;
   kp.u_in = static_cast<const float2 *>(u_in);
   kp.u_out = static_cast<float2 *>(u_out);
@@ -424,7 +436,7 @@ dop_status dop_psf_backward(dop_context *ctx, const dop_problem *prob, const flo
     return fail(DOP_ERR_INVALID_ARG, "misaligned array");
   if ((s = check_ws(prob, DOP_OP_PSF_BACKWARD, ws, ws_bytes)) != DOP_OK) return s;
   if ((s = check_ctx_device(ctx)) != DOP_OK) return s;
-  const size_t nn = (size_t)prob->n * prob->n;
+  const size_t nn = (size_t)doe_rows(prob) * prob->n;
   const int up = upsample_factor(prob);
   // with an upsampled design the passes accumulate the n x n fine gradient in
   // the workspace tail; its s x s block sums are the coarse gradient
@@ -436,7 +448,7 @@ dop_status dop_psf_backward(dop_context *ctx, const dop_problem *prob, const flo
     kp.in_mode = IN_GRAD;
     kp.out_mode = OUT_GRADH;
     kp.full = 0;
-    kp.nrows_out = prob->n;
+    kp.nrows_out = doe_rows(prob);
     kp.first = (k == 0);
     kp.adjoint = 1;
     kp.zl = -kp.zl;  // conj(H) = H at -z (the band limit depends on |z| only)
@@ -449,8 +461,9 @@ dop_status dop_psf_backward(dop_context *ctx, const dop_problem *prob, const flo
     if (s != DOP_OK) return s;
   }
   if (up > 1) {
-    const hipError_t e = launch_upsample_adjoint(DOP_UPSAMPLE_NEAREST, prob->n / up, up, grad_fine,
-                                                 grad_h, static_cast<hipStream_t>(stream));
+    const hipError_t e = launch_upsample_nearest_adjoint(doe_rows(prob) / up, prob->n / up, up,
+                                                         grad_fine, grad_h,
+                                                         static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
       return fail(DOP_ERR_DEVICE, "upsample adjoint launch failed: %s", hipGetErrorString(e));
   }

@@ -12,10 +12,17 @@ namespace dop {
 dop_status fail(dop_status s, const char *fmt, ...);
 void clear_error();
 
+// Grid and DOE extents of a problem: columns are m and n, rows my and ny
+// (0 there means square).
+inline int grid_cols(const dop_problem *p) { return p->m; }
+inline int grid_rows(const dop_problem *p) { return p->my > 0 ? p->my : p->m; }
+inline int doe_cols(const dop_problem *p) { return p->n; }
+inline int doe_rows(const dop_problem *p) { return p->ny > 0 ? p->ny : p->n; }
+
 // Full validation of a problem description (no device access).
 dop_status validate_problem(const dop_problem *prob);
 
-// Workspace bytes of any operation on `prob` (one M x M complex64 field).
+// Workspace bytes of any operation on `prob` (one My x Mx complex64 field).
 size_t workspace_bytes(const dop_problem *prob);
 
 // Enqueue the whole PSF of `prob` (all wavelengths) on `stream`.

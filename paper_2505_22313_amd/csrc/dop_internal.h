@@ -33,20 +33,21 @@ enum OutMode : int {
 
 // Everything one wavelength's five passes need.  Passed by value.
 struct KParams {
-  float2 *ws;            // M x M c64 workspace
+  float2 *ws;            // My x Mx c64 workspace (row pitch Mx + kRowPad)
   const float2 *tw;      // twiddle table, kTwN entries
-  int n, m, plan;         // plan id of M (plan_id)
+  int n;                 // DOE columns Nx (row length of every N-wide array)
+  int plan;              // plan id of the grid (plan_id)
   int nrows_in;          // rows of the padded input that may be nonzero
   int nrows_out;         // rows of the output plane that are needed
-  int p0;                // (M - N) / 2
+  int p0x, p0y;          // (Mx - Nx) / 2, (My - Ny) / 2
   int in_mode, out_mode;
   int full;              // 1: output the whole M x M plane (centred)
   int first;             // 1: overwrite the accumulator, 0: add to it
   int adjoint;           // 1: adjoint pass (H conjugated through zl < 0)
   const float *h;        // heights (IN_PHASE, OUT_GRADH): row y, column x of
-                         // the N x N map is h[(y >> up_log2) * nh + (x >> up_log2)]
+                         // the Ny x Nx map is h[(y >> up_log2) * nh + (x >> up_log2)]
   int up_log2;           // log2 of the nearest-neighbour upsampling factor
-  int nh;                // row length of h: N >> up_log2
+  int nh;                // row length of h: Nx >> up_log2
   const float *amp;      // N x N amplitude or NULL
   const float2 *u_in;    // N x N field (IN_FIELD)
   const float2 *saved_in;// N x N field U_k (IN_GRAD)
@@ -59,13 +60,16 @@ struct KParams {
   double zl;             // z / lambda_k (turns at normal incidence); -z / lambda_k
                          // for the adjoint, whose transfer function is conj(H)
   double lam;            // lambda_k
-  double inv_mdx;        // 1 / (M dx)
-  double flim;           // band limit on |fx| and |fy| (infinity: none)
-  float wk_m4;           // w_k / M^4: PSF weight times the squared 1/M^2 of the
-                         // inverse DFT, which the passes leave to the output
+  double inv_mdx;        // 1 / (Mx dx)
+  double inv_mdy;        // 1 / (My dx)
+  double flim_x;         // band limit on |fx| (infinity: none)
+  double flim_y;         // band limit on |fy| (infinity: none)
+  float wk_m4;           // w_k / (My Mx)^2: PSF weight times the squared
+                         // 1/(My Mx) of the inverse DFT, which the passes
+                         // leave to the output
   float two_wk;          // 2 w_k
-  float ck_m2;           // 2 pi (n_k - 1) / lambda_k / M^2
-  float inv_m2;          // 1 / M^2 (inverse-DFT normalisation of output fields)
+  float ck_m2;           // 2 pi (n_k - 1) / lambda_k / (My Mx)
+  float inv_m2;          // 1 / (My Mx) (inverse-DFT normalisation of output fields)
 };
 
 constexpr int kNumPasses = 5;
@@ -75,14 +79,15 @@ constexpr int kNumPasses = 5;
 // after the last one.
 hipError_t launch_wavelength(const KParams &p, hipStream_t stream, hipEvent_t *ev);
 
-// Plan id of grid size M: log2(M) for a power of two in [16, 131072], a
-// larger id for each supported grid that is not a power of two, -1 if M has
-// no plan.
-int plan_id(int m);
+// Plan id of the My x Mx grid (mx columns, my rows): log2(M) for a square
+// power of two M in [16, 131072], a larger id for each grid of the plan
+// table, -1 if the grid has no plan.
+int plan_id(int mx, int my);
 
-// The supported grids that are not powers of two: writes up to `max` sizes
-// and returns how many there are.
-int np2_grids(int *out, int max);
+// The grids of the plan table (square grids that are not powers of two,
+// and rectangular grids): writes up to `max` (rows, columns) pairs and
+// returns how many there are.
+int table_grids(int *rows, int *cols, int max);
 
 // Tile geometry of a pass plan (host-side copy of the compile-time plan,
 // used for reporting and tests).
@@ -98,6 +103,10 @@ hipError_t launch_upsample(int kind, int nc, int s, const float *coarse, float *
                            hipStream_t stream);
 hipError_t launch_upsample_adjoint(int kind, int nc, int s, const float *grad_fine,
                                    float *grad_coarse, hipStream_t stream);
+// Nearest-neighbour adjoint (s x s block sums) of a rectangular coarse grid of
+// ncy rows and ncx columns.
+hipError_t launch_upsample_nearest_adjoint(int ncy, int ncx, int s, const float *grad_fine,
+                                           float *grad_coarse, hipStream_t stream);
 
 }  // namespace dop
 

@@ -153,7 +153,8 @@ class MockExecutor : public Executor {
  public:
   MockExecutor(int slots, double us_per_mpix) : end_(slots, 0.0), us_per_mpix_(us_per_mpix) {}
   dop_status start(int slot, Request &r, void *, size_t) override {
-    const double mpix = (double)r.prob.n_lambda * r.prob.m * (double)r.prob.m / 1e6;
+    const double mpix =
+        (double)r.prob.n_lambda * grid_cols(&r.prob) * (double)grid_rows(&r.prob) / 1e6;
     end_[slot] = now_s() + us_per_mpix_ * mpix * 1e-6;
     return DOP_OK;
   }
@@ -195,7 +196,7 @@ struct dop_server {
 
   // padded pixels x wavelengths: the request's share of GPU time
   static double work(const Request &r) {
-    return (double)r.prob.n_lambda * (double)r.prob.m * (double)r.prob.m;
+    return (double)r.prob.n_lambda * (double)grid_cols(&r.prob) * (double)grid_rows(&r.prob);
   }
 
   void finish(Request *r, dop_status st) {

@@ -99,18 +99,20 @@ __global__ __launch_bounds__(256) void k_up_nearest(int nc, int s, const float *
   }
 }
 
-// Sum of each s x s block, rows in order, columns in order within a row.
-__global__ __launch_bounds__(256) void k_up_nearest_adj(int nc, int s, const float *__restrict__ g,
+// Sum of each s x s block of a (ncy s) x (ncx s) map, rows in order, columns
+// in order within a row.
+__global__ __launch_bounds__(256) void k_up_nearest_adj(int ncy, int ncx, int s,
+                                                        const float *__restrict__ g,
                                                         float *__restrict__ out) {
-  const int nf = nc * s;
-  for (int i = blockIdx.y; i < nc; i += gridDim.y) {
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nc; k += gridDim.x * blockDim.x) {
+  const int nfx = ncx * s;
+  for (int i = blockIdx.y; i < ncy; i += gridDim.y) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < ncx; k += gridDim.x * blockDim.x) {
       float a = 0.f;
       for (int dy = 0; dy < s; ++dy) {
-        const float *row = g + (size_t)(i * s + dy) * nf + (size_t)k * s;
+        const float *row = g + (size_t)(i * s + dy) * nfx + (size_t)k * s;
         for (int dx = 0; dx < s; ++dx) a += row[dx];
       }
-      out[(size_t)i * nc + k] = a;
+      out[(size_t)i * ncx + k] = a;
     }
   }
 }
@@ -278,12 +280,18 @@ hipError_t launch_upsample(int kind, int nc, int s, const float *coarse, float *
   return hipGetLastError();
 }
 
+hipError_t launch_upsample_nearest_adjoint(int ncy, int ncx, int s, const float *grad_fine,
+                                           float *grad_coarse, hipStream_t stream) {
+  const dim3 grid(cdiv(ncx, 256) < 64 ? cdiv(ncx, 256) : 64, ncy < 4096 ? ncy : 4096);
+  hipLaunchKernelGGL(k_up_nearest_adj, grid, dim3(256), 0, stream, ncy, ncx, s, grad_fine,
+                     grad_coarse);
+  return hipGetLastError();
+}
+
 hipError_t launch_upsample_adjoint(int kind, int nc, int s, const float *grad_fine,
                                    float *grad_coarse, hipStream_t stream) {
   if (kind == 0) {
-    const dim3 grid(cdiv(nc, 256) < 64 ? cdiv(nc, 256) : 64, nc < 4096 ? nc : 4096);
-    hipLaunchKernelGGL(k_up_nearest_adj, grid, dim3(256), 0, stream, nc, s, grad_fine,
-                       grad_coarse);
+    return launch_upsample_nearest_adjoint(nc, nc, s, grad_fine, grad_coarse, stream);
   } else {
     const dim3 grid(cdiv(nc, kAdjTile), cdiv(nc, kAdjTile));
     if (s <= 8)

@@ -53,11 +53,66 @@ def good(**kw):
 
 
 def test_workspace_size_valid():
-    for m in [16, 1024, 65536, 131072, 240, 720, 1440, 3072, 3600, 28800, 40000]:
+    for m in [16, 1024, 65536, 131072, 240, 720, 1440, 2144, 3072, 3600, 28800, 40000]:
         st, b = _ws(good(n=m // 2, m=m))
         assert st == L.DOP_OK and b == 8 * m * (m + 16)
     for op in (L.DOP_OP_PROPAGATE, L.DOP_OP_PSF, L.DOP_OP_PSF_BACKWARD):
         assert _ws(good(), op)[0] == L.DOP_OK
+
+
+RECT_GRIDS = [(720, 240), (512, 2048), (240, 2144), (5360, 240), (16080, 10720),
+              (128640, 85760)]
+
+
+def test_workspace_size_rectangular():
+    """Rectangular grids (rows x columns): one My x (Mx + 16) complex64 field;
+    the DOE is Ny x Nx; the backward of an upsampled design adds its fine
+    gradient after the field."""
+    for my, mx in RECT_GRIDS + [(2144, 2144)]:
+        st, b = _ws(good(n=(my // 2, mx // 2), m=(my, mx)))
+        assert st == L.DOP_OK, (my, mx, L.last_error())
+        assert b == 8 * my * (mx + 16)
+    p = good(n=(64320, 42880), m=(128640, 85760), upsample=4)
+    assert p.h_shape == (16080, 10720) and p.out_shape == (64320, 42880)
+    st, b = _ws(p, L.DOP_OP_PSF_BACKWARD)
+    field = 8 * 128640 * (85760 + 16)
+    assert st == L.DOP_OK and b == ((field + 255) & ~255) + 4 * 64320 * 42880
+    # the paper's grid fits one MI355X: 88.3 GB
+    assert 88e9 < field < 88.5e9
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=(100, 200), m=(240, 720)), L.DOP_ERR_UNSUPPORTED),   # transpose of a listed grid
+    (dict(n=(100, 100), m=(1024, 512)), L.DOP_ERR_UNSUPPORTED),  # rectangular powers of two
+    (dict(n=(300, 100), m=(240, 720)), L.DOP_ERR_UNSUPPORTED),
+    (dict(n=(721, 100), m=(720, 240)), L.DOP_ERR_INVALID_ARG),   # ny > my
+    (dict(n=(100, 241), m=(720, 240)), L.DOP_ERR_INVALID_ARG),   # nx > mx
+    (dict(n=(100, 96), m=(720, 240), upsample=8), L.DOP_ERR_INVALID_ARG),  # 8 does not divide 100
+])
+def test_rectangular_validation(kw, code):
+    st, _ = _ws(good(**kw))
+    assert st == code, (kw, L.status_string(st), L.last_error())
+
+
+def test_unsupported_grid_lists_plans():
+    st, _ = _ws(good(n=(100, 100), m=(1000, 1000)))
+    assert st == L.DOP_ERR_UNSUPPORTED
+    msg = L.last_error()
+    assert "128640x85760" in msg and "2144^2" in msg and "40000^2" in msg
+
+
+def test_negative_rows_rejected():
+    p = good()
+    p._c.ny = -1
+    assert _ws(p)[0] == L.DOP_ERR_INVALID_ARG
+    p = good()
+    p._c.my = -4
+    assert _ws(p)[0] == L.DOP_ERR_INVALID_ARG
+    # 0 means square
+    p = good()
+    p._c.ny = 0
+    p._c.my = 0
+    assert _ws(p) == (L.DOP_OK, 8 * 1024 * 1040)
 
 
 @pytest.mark.parametrize("kw,code", [

@@ -28,7 +28,8 @@ def log(*a):
 
 
 def pass_bytes(n, m, k_first, amp=False):
-    """Algorithmic HBM bytes of each pass for one wavelength (crop output).
+    """Algorithmic HBM bytes of each pass for one wavelength (crop output);
+    n and m are ints (square) or (rows, columns).
 
     A : read h (and amp) N^2, write N rows of the M x M c64 field
     B : read N rows, write M rows
@@ -36,9 +37,11 @@ def pass_bytes(n, m, k_first, amp=False):
     B': read M rows, write N rows
     A': read N rows, read-modify-write the N^2 fp32 PSF (write only for k=0)
     """
-    f = 8.0 * n * m  # N rows of c64
-    full = 8.0 * m * m
-    nn = float(n) * n
+    ny, nx = (n, n) if np.ndim(n) == 0 else n
+    my, mx = (m, m) if np.ndim(m) == 0 else m
+    f = 8.0 * ny * mx  # Ny rows of c64
+    full = 8.0 * my * mx
+    nn = float(ny) * nx
     return {
         "pass_a_fwd": nn * 4 * (2 if amp else 1) + f,
         "pass_b_fwd": f + full,
@@ -202,18 +205,28 @@ def paper_table2_measure(api, wl, torch):
         dict(name="imaging_conventional_4x_upsampling", nc=5000, s=4, dx=0.5, m=40000,
              lams=list(np.linspace(0.4, 0.7, 6)), z=80000.0, steps=6,
              paper="9 h / 20000 iterations = 1.62 s per iteration on 12x A100 80 GB (mesh [6, 2])"),
+        # 32.16 x 21.44 mm large-area CHD, 2 um features at 4x (0.5 um), 128640 x 85760 grid,
+        # z = 6 cm (the paper's hologram wavelength is not stated for it; 520.6 nm here)
+        dict(name="large_area_chd_conventional_4x_upsampling", nc=(16080, 10720), s=4, dx=0.5,
+             m=(128640, 85760), lams=[0.5206], z=60000.0, steps=3,
+             paper="13 h / 3000 iterations = 15.6 s per iteration on 16x A100 80 GB (mesh [1, 16])"),
     ]
     res = {}
     for c in cases:
-        n = c["nc"] * c["s"]
+        ncy, ncx = (c["nc"], c["nc"]) if np.ndim(c["nc"]) == 0 else c["nc"]
+        my, mx = (c["m"], c["m"]) if np.ndim(c["m"]) == 0 else c["m"]
+        ny, nx = ncy * c["s"], ncx * c["s"]
         lams = np.asarray(c["lams"])
-        prob = api.Problem(n, c["m"], c["dx"], c["z"], lams, wl.cauchy_index(lams), upsample=c["s"])
-        h0 = torch.from_numpy(wl.uniform_heights(c["nc"], seed=c["nc"])).cuda()
-        target = torch.from_numpy(wl.gaussian_target(n, 50.0, total=len(lams) * float(n) * n)).cuda()
+        log(f"paper design {c['name']}")
+        prob = api.Problem((ny, nx), (my, mx), c["dx"], c["z"], lams, wl.cauchy_index(lams),
+                           upsample=c["s"])
+        h0 = torch.from_numpy(wl.uniform_heights((ncy, ncx), seed=ncy)).cuda()
+        target = torch.from_numpy(wl.gaussian_target((ny, nx), 50.0,
+                                                     total=len(lams) * float(ny) * nx)).cuda()
         design_loop(h0, prob, target, steps=2)  # warm-up
         _, losses, dt = design_loop(h0, prob, target, steps=c["steps"])
-        res[c["name"]] = {"design": f"{c['nc']}^2 at 2 um, nearest x{c['s']} -> {n}^2, "
-                                    f"grid {c['m']}^2, {len(lams)} wavelength(s)",
+        res[c["name"]] = {"design": f"{ncy}x{ncx} at 2 um, nearest x{c['s']} -> {ny}x{nx}, "
+                                    f"grid {my}x{mx}, {len(lams)} wavelength(s)",
                           "s_per_iteration": round(dt, 4), "steps": c["steps"],
                           "loss_first": losses[0], "loss_last": losses[-1],
                           "paper": c["paper"]}
@@ -364,6 +377,27 @@ def variants_measure(api, wl, torch, p, hd, ctx, base_ms):
         "ms_per_step": round(ms, 1), "value": round(3 * float(m_h) ** 2 / (ms * 1e-3) / 1e6, 1),
         "passes_alg_gbs": {k: round(pb[k] / (v[1] / v[0] * 1e-3) / 1e9, 1) for k, v in prof.items()}}
     del hh, oh
+    ctx.release_workspaces()
+    torch.cuda.empty_cache()
+    # the paper's largest grid (Table 2): a 32.16 x 21.44 mm DOE at 0.5 um, 64320 x 42880,
+    # padded to 128640 x 85760 (radix-67 stages on both axes, an 88 GB workspace)
+    ny, nx, my, mx = 64320, 42880, 128640, 85760
+    hp = torch.rand((ny, nx), generator=torch.Generator(device="cuda").manual_seed(18),
+                    device="cuda") * 1.2
+    pp = api.Problem((ny, nx), (my, mx), 0.5, 60000.0, lams3, wl.cauchy_index(lams3))
+    op = torch.empty((ny, nx), dtype=torch.float32, device="cuda")
+    ctx.profile_enable(True)
+    ms = _event_ms(torch, lambda: api.psf(hp, pp, out=op, ctx=ctx), 1)
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    pb = pass_bytes((ny, nx), (my, mx), k_first=False)
+    res["paper_grid"] = {
+        "doe": f"{ny}x{nx}", "grid": f"{my}x{mx}", "n_lambda": 3,
+        "workspace_gb": round(api.workspace_size(pp) / 1e9, 1), "ms_per_step": round(ms, 1),
+        "value": round(3 * float(my) * mx / (ms * 1e-3) / 1e6, 1),
+        "passes_avg_ms": {k: round(v[1] / v[0], 3) for k, v in prof.items()},
+        "passes_alg_gbs": {k: round(pb[k] / (v[1] / v[0] * 1e-3) / 1e9, 1) for k, v in prof.items()}}
+    del hp, op
     ctx.release_workspaces()
     torch.cuda.empty_cache()
     return res

@@ -171,7 +171,7 @@ def psf(h, dx, z, m, lams, n_index, weights=None, amp=None, out_mode="crop",
     return (acc, fields) if return_fields else acc
 
 
-def psf_lowmem(h, dx, z, m, lam, n_index, block=1024, log=None):
+def psf_lowmem(h, dx, z, m, lam, n_index, block=1024, log=None, rows=None):
     """``psf`` for one wavelength (CROP, no amplitude mask, weight 1) on grids
     whose full-plane temporaries do not fit in memory (square or
     rectangular).
@@ -182,8 +182,11 @@ def psf_lowmem(h, dx, z, m, lam, n_index, block=1024, log=None):
     array, and H is applied one block of rows at a time.  Rows of the padded
     field outside the DOE are zero, so their row DFTs are skipped; only the
     N crop rows of the inverse row DFT are taken.  Peak memory is about
-    16 M^2 bytes plus a few blocks.  Returns the N x N float64 PSF.
+    16 M^2 bytes plus a few blocks.  Returns the N x N float64 PSF; with
+    ``rows`` (indices into the crop) returns (psf[rows], sum, max) instead,
+    the sum and max taken over the whole crop without holding it.
     """
+    keep = None if rows is None else np.asarray(rows, dtype=np.int64)
     h = np.asarray(h)
     ny, nx = h.shape
     my, mx = grid_shape(m)
@@ -212,13 +215,21 @@ def psf_lowmem(h, dx, z, m, lam, n_index, block=1024, log=None):
         c1 = min(mx, c0 + block)
         ep[:, c0:c1] = sfft.ifft(ep[:, c0:c1], axis=0, workers=WORKERS)
     say("inverse column DFTs done")
-    out = np.empty((ny, nx), dtype=np.float64)
+    out = np.empty((ny, nx) if keep is None else (len(keep), nx), dtype=np.float64)
+    total, peak = 0.0, 0.0
     for r0 in range(0, ny, block):
         r1 = min(ny, r0 + block)
         u = sfft.ifft(ep[py + r0:py + r1], axis=1, workers=WORKERS)[:, px:px + nx]
-        out[r0:r1] = u.real * u.real + u.imag * u.imag
+        p = u.real * u.real + u.imag * u.imag
+        if keep is None:
+            out[r0:r1] = p
+        else:
+            sel = (keep >= r0) & (keep < r1)
+            out[sel] = p[keep[sel] - r0]
+            total += float(p.sum())
+            peak = max(peak, float(p.max()))
     say("inverse row DFTs done")
-    return out
+    return out if keep is None else (out, total, peak)
 
 
 def psf_backward(h, dx, z, m, lams, n_index, grad_psf, weights=None, amp=None,

@@ -143,10 +143,14 @@ def smooth_noise(n, seed, sigma_px=8.0, std=0.02, truncate=4.0):
 
 
 def gaussian_target(n, sigma_px, total):
-    """Gaussian spot about pixel (n/2, n/2) scaled so that its sum is `total`."""
-    c = np.arange(n, dtype=np.float64) - n // 2
-    g = np.exp(-(c[:, None] ** 2 + c[None, :] ** 2) / (2.0 * sigma_px ** 2))
-    return (g * (total / g.sum())).astype(np.float32)
+    """Gaussian spot about pixel (ny/2, nx/2) scaled so that its sum is
+    `total`; n is an int (square) or (rows, columns).  Formed as the product
+    of its two axis profiles (float32), so large targets need no FP64 plane."""
+    ny, nx = shape2(n)
+    gy = np.exp(-((np.arange(ny, dtype=np.float64) - ny // 2) ** 2) / (2.0 * sigma_px ** 2))
+    gx = np.exp(-((np.arange(nx, dtype=np.float64) - nx // 2) ** 2) / (2.0 * sigma_px ** 2))
+    scale = total / (gy.sum() * gx.sum())
+    return (gy * scale).astype(np.float32)[:, None] * gx.astype(np.float32)[None, :]
 
 
 def square_lens_amp(n):

@@ -2,11 +2,13 @@
 0.5 um (64,320 rows x 42,880 columns) padded to 128,640 x 85,760 (Table 2,
 the large-area hologram designs the paper ran on 16 A100s; an 88 GB
 workspace here).  Its axes carry the prime factor 67 (128,640 = 2^7 3 5 67,
-85,760 = 2^8 5 67).  An FP64 oracle of the whole field would need about
-180 GB of host memory, so these are properties that hold at any size and
-pin every pass: z = 0 is the identity, Parseval on the full plane, and the
-focus of an ideal lens against the exact on-axis Rayleigh-Sommerfeld value
-and the sinc^2 profile of the rectangular pupil along both axes.
+85,760 = 2^8 5 67).  Checked: the paper's own upsampled design problem
+against an FP64 oracle golden (12 whole PSF rows, total and peak; the
+oracle needs about 200 GB of host memory, so the golden is written once by
+tests/golden/make_paper_grid_golden.py), and properties that hold at any
+size and pin every pass: z = 0 is the identity, Parseval on the full plane,
+and the focus of an ideal lens against the exact on-axis Rayleigh-Sommerfeld
+value and the sinc^2 profile of the rectangular pupil along both axes.
 """
 
 import numpy as np
@@ -94,4 +96,35 @@ def test_paper_grid_lens_focus(api):
     # the widths differ: the x profile is wider than the y profile
     assert win[8, 10] > win[10, 8]
     del h, p
+    free(api)
+
+
+def test_paper_grid_psf_rows_vs_oracle(api):
+    """The paper's own large-area problem at full size against the FP64
+    oracle: a seeded 16,080 x 10,720 design at 2 um, 4x nearest upsampling
+    fused into the first pass, the 128,640 x 85,760 grid, 520.6 nm, z = 60 mm.
+    12 whole PSF rows (rel-L2 <= 1e-4), the crop's total (1e-5) and peak
+    (1e-4) against tests/golden/psf_paper_grid_rows.npz, which
+    make_paper_grid_golden.py writes with the oracle alone."""
+    import os
+    print("paper grid: rows vs oracle golden", flush=True)
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "psf_paper_grid_rows.npz"))
+    ncy, ncx, s = int(g["ncy"]), int(g["ncx"]), int(g["s"])
+    assert (ncy * s, ncx * s, int(g["my"]), int(g["mx"])) == (NY, NX, MY, MX)
+    hc = torch.from_numpy(wl.uniform_heights((ncy, ncx), seed=int(g["seed"]))).cuda()
+    prob = api.Problem((NY, NX), (MY, MX), float(g["dx"]), float(g["z"]), [float(g["lam"])],
+                       [float(g["n_index"])], upsample=s)
+    p = api.psf(hc, prob)
+    rows = torch.from_numpy(g["rows"]).cuda()
+    got = p[rows].double().cpu().numpy()
+    want = g["psf_rows"].astype(np.float64)
+    err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+    total = sum(float(p[r0:r0 + 8192].sum(dtype=torch.float64).item()) for r0 in range(0, NY, 8192))
+    peak = float(p.max().item())
+    print(f"  rows rel-L2 {err:.3e}, total {total / float(g['total']) - 1:.2e}, "
+          f"peak {peak / float(g['peak']) - 1:.2e}", flush=True)
+    assert err < 1e-4
+    assert abs(total / float(g["total"]) - 1) < 1e-5
+    assert abs(peak / float(g["peak"]) - 1) < 1e-4
+    del hc, p
     free(api)

@@ -569,3 +569,14 @@ def test_rect_psf_lowmem_equals_psf():
     a = oracle.psf(h, 0.5, 300.0, (96, 160), [0.55], [1.46])
     b = oracle.psf_lowmem(h, 0.5, 300.0, (96, 160), 0.55, 1.46, block=16)
     assert rel(b, a) < 1e-12
+
+
+def test_psf_lowmem_rows_mode():
+    """Selected rows, the sum and the max of the crop without holding it: the
+    same values as the whole-crop result."""
+    h = np.random.default_rng(25).uniform(0, 1.2, (40, 72))
+    full = oracle.psf_lowmem(h, 0.5, 300.0, (96, 160), 0.55, 1.46, block=16)
+    rows = [0, 7, 15, 16, 33, 39]
+    got, total, peak = oracle.psf_lowmem(h, 0.5, 300.0, (96, 160), 0.55, 1.46, block=16, rows=rows)
+    assert np.array_equal(got, full[rows])
+    assert abs(total - full.sum()) < 1e-12 * full.sum() and peak == full.max()

@@ -417,33 +417,43 @@ struct LastRegs {
 // ---------------------------------------------------------------------------
 // Radix-67 Stockham stage.  67 points per item do not fit in registers, so
 // the stage works through the tile in LDS, in place:
-//  1. fold: one thread per item reads v_t (after the stage twiddles) and
-//     writes v_t + v_{67-t} to slot t and v_t - v_{67-t} to slot 67 - t,
-//     t = 1..33 (slot 0 keeps v_0);
-//  2. three threads per item each form 11 output pairs from the folded
-//     values, with X_k, X_{67-k} = v_0 + sum_t s_t cos(2 pi t k / 67)
+//  1. fold: for every item and t = 1..33 (one thread per pair), read v_t and
+//     v_{67-t} (after the stage twiddles) and write v_t + v_{67-t} to slot t
+//     and v_t - v_{67-t} to slot 67 - t (slot 0 keeps v_0);
+//  2. three or four threads per item (whichever spreads the tile's
+//     wavefronts evenly over the four SIMDs) each form a share of the 33
+//     output pairs from the folded values, X_k, X_{67-k} = v_0 + sum_t s_t cos(2 pi t k / 67)
 //     -/+ i sum_t d_t sin(2 pi t k / 67) (forward sign; the symmetric form of
-//     the direct DFT, 2 real multiply-adds per input pair and output), the
-//     constants folded in at compile time; the share rb = 0, 1, 2 is uniform
-//     across a wavefront so that the three code paths do not diverge;
+//     the direct DFT, 2 real multiply-adds per input pair and output), with
+//     the constants folded in at compile time; a share is uniform across a
+//     wavefront so that the code paths of the shares do not diverge;
 //  3. the outputs go to the stage's Stockham positions, in LDS or through the
 //     store functor.
 // Inputs come from LDS or the load functor, never from registers, and
 // outputs never go to registers.
 // ---------------------------------------------------------------------------
 constexpr int kPH = (kP - 1) / 2;  // folded input pairs
-constexpr int kPB = 11;            // output pairs per thread (kPH / 3)
-static_assert(3 * kPB == kPH, "three output shares");
+// With NSH shares per item, share rb covers output pairs k = share_k0 ..
+// share_k0 + share_np - 1: 11 + 11 + 11 or 9 + 8 + 8 + 8.
+__host__ __device__ constexpr int share_np(int nsh, int rb) {
+  return nsh == 3 ? 11 : (rb == 0 ? 9 : 8);
+}
+__host__ __device__ constexpr int share_k0(int nsh, int rb) {
+  return nsh == 3 ? 1 + 11 * rb : (rb == 0 ? 1 : 10 + 8 * (rb - 1));
+}
+constexpr int kPBMax = 11;
+static_assert(share_k0(3, 2) + share_np(3, 2) == kPH + 1, "three shares cover 1..33");
+static_assert(share_k0(4, 3) + share_np(4, 3) == kPH + 1, "four shares cover 1..33");
 
-template <class G, int RB, bool INV>
-DEV void prime_outputs(const float2 *lds, const int e0, float2 (&o)[2 * kPB + 1]) {
+template <class G, int NSH, int RB, bool INV>
+DEV void prime_outputs(const float2 *lds, const int e0, float2 (&o)[2 * kPBMax + 1]) {
   constexpr int STEP = (G::L / kP) * G::SJ;
-  constexpr int K0 = 1 + kPB * RB;
+  constexpr int K0 = share_k0(NSH, RB), NP = share_np(NSH, RB);
   const float2 x0 = lds[e0];
-  float2 a[kPB], q[kPB];
+  float2 a[NP], q[NP];
   float2 sum = x0;
 #pragma unroll
-  for (int i = 0; i < kPB; ++i) {
+  for (int i = 0; i < NP; ++i) {
     a[i] = x0;
     q[i] = make_float2(0.f, 0.f);
   }
@@ -452,22 +462,22 @@ DEV void prime_outputs(const float2 *lds, const int e0, float2 (&o)[2 * kPB + 1]
     const float2 sv = lds[e0 + t * STEP], dv = lds[e0 + (kP - t) * STEP];
     if constexpr (RB == 0) sum = cadd(sum, sv);
 #pragma unroll
-    for (int i = 0; i < kPB; ++i) {
+    for (int i = 0; i < NP; ++i) {
       const int e = (t * (K0 + i)) % kP;
-      const float c = UnitRoots<kP>::c[e], sn = UnitRoots<kP>::s[e];
+      const float c = UnitRoots<kP>::c[e], sn_ = UnitRoots<kP>::s[e];
       a[i].x += sv.x * c;
       a[i].y += sv.y * c;
-      q[i].x += dv.x * sn;
-      q[i].y += dv.y * sn;
+      q[i].x += dv.x * sn_;
+      q[i].y += dv.y * sn_;
     }
   }
 #pragma unroll
-  for (int i = 0; i < kPB; ++i) {
+  for (int i = 0; i < NP; ++i) {
     const float2 iq = INV ? mul_pi(q[i]) : mul_mi(q[i]);
     o[2 * i] = cadd(a[i], iq);      // X_{K0 + i}
     o[2 * i + 1] = csub(a[i], iq);  // X_{67 - K0 - i}
   }
-  o[2 * kPB] = sum;                 // X_0 (share 0)
+  o[2 * kPBMax] = sum;              // X_0 (share 0)
 }
 
 template <class G, bool INV, bool FIRST, bool LAST, int NS, int TWMUL, int SRC, int SNK,
@@ -478,48 +488,52 @@ DEV void stage_prime(float2 *lds, const float2 *twl, const LoadF &ld, const Stor
                 "a radix-67 stage reads and writes LDS or functors, not registers");
   constexpr int LR = G::L / kP, ITEMS = LR * G::NB;
   auto at = [](int j, int b) { return j * G::SJ + b * G::SB; };
-  // 1. fold, one thread per item, in place
-  for (int it = tid; it < ITEMS; it += G::T) {
+  // 1. fold, one thread per (item, pair), in place; item fastest so that
+  // neighbouring threads touch neighbouring LDS words
+  for (int u = tid; u < ITEMS * (kPH + 1); u += G::T) {
+    const int it = u % ITEMS, t = u / ITEMS;
     int j, b;
     decode_item<G, kP>(it, j, b);
     if (b >= nb_act) continue;
+    if (t == 0) {
+      if constexpr (SRC == SRC_FN) lds[at(j, b)] = ld(j, b);
+      continue;
+    }
     const int k = FIRST ? 0 : (is_pow2c(NS) ? j & (NS - 1) : (int)((unsigned)j % NS));
-    auto in = [&](int t) {
+    auto in = [&](int tt) {
       float2 x;
-      if constexpr (SRC == SRC_FN) x = ld(j + t * LR, b);
-      else x = lds[at(j + t * LR, b)];
+      if constexpr (SRC == SRC_FN) x = ld(j + tt * LR, b);
+      else x = lds[at(j + tt * LR, b)];
       if constexpr (!FIRST) {
-        const float2 w = twl[(t * k) * TWMUL];
+        const float2 w = twl[(tt * k) * TWMUL];
         x = INV ? cmulc(x, w) : cmul(x, w);
       }
       return x;
     };
-    if constexpr (SRC == SRC_FN) lds[at(j, b)] = ld(j, b);
-#pragma unroll 3
-    for (int t = 1; t <= kPH; ++t) {
-      const float2 u = in(t), w = in(kP - t);
-      lds[at(j + t * LR, b)] = cadd(u, w);
-      lds[at(j + (kP - t) * LR, b)] = csub(u, w);
-    }
+    const float2 v1 = in(t), v2 = in(kP - t);
+    lds[at(j + t * LR, b)] = cadd(v1, v2);
+    lds[at(j + (kP - t) * LR, b)] = csub(v1, v2);
   }
   if constexpr (FIRST) hook();
   __syncthreads();
   // 2. outputs: wavefront w takes share w / IW of items (w % IW) * 64 + lane
   constexpr int IW = (ITEMS + 63) / 64;
-  static_assert(3 * IW * 64 <= G::T, "one output share per thread");
+  constexpr int NSH = (3 * IW) % 4 == 0 || 4 * IW * 64 > G::T ? 3 : 4;
+  static_assert(NSH * IW * 64 <= G::T, "one output share per thread");
   const int wv = tid >> 6, rb = wv / IW, it = (wv % IW) * 64 + (tid & 63);
   int j = 0, b = 0;
-  bool act = rb < 3 && it < ITEMS;
+  bool act = rb < NSH && it < ITEMS;
   if (act) {
     decode_item<G, kP>(it, j, b);
     act = b < nb_act;
   }
-  float2 o[2 * kPB + 1];
+  float2 o[2 * kPBMax + 1];
   if (act) {
     const int e0 = at(j, b);
-    if (rb == 0) prime_outputs<G, 0, INV>(lds, e0, o);
-    else if (rb == 1) prime_outputs<G, 1, INV>(lds, e0, o);
-    else prime_outputs<G, 2, INV>(lds, e0, o);
+    if (rb == 0) prime_outputs<G, NSH, 0, INV>(lds, e0, o);
+    else if (rb == 1) prime_outputs<G, NSH, 1, INV>(lds, e0, o);
+    else if (NSH == 3 || rb == 2) prime_outputs<G, NSH, 2, INV>(lds, e0, o);
+    else prime_outputs<G, NSH, NSH == 3 ? 2 : 3, INV>(lds, e0, o);
   }
   // 3. output t of item (j, b) goes to (j - k) * 67 + k + t * NS, k = j mod NS
   constexpr bool TO_LDS = !LAST || SNK == SNK_LDS;
@@ -531,13 +545,15 @@ DEV void stage_prime(float2 *lds, const float2 *twl, const LoadF &ld, const Stor
       if constexpr (TO_LDS) lds[at(base + t * NS, b)] = val;
       else st(base + t * NS, b, val);
     };
-    const int k0 = 1 + kPB * rb;
+    const int k0 = share_k0(NSH, rb), np = share_np(NSH, rb);
 #pragma unroll
-    for (int i = 0; i < kPB; ++i) {
-      put(k0 + i, o[2 * i]);
-      put(kP - k0 - i, o[2 * i + 1]);
+    for (int i = 0; i < kPBMax; ++i) {
+      if (i < np) {
+        put(k0 + i, o[2 * i]);
+        put(kP - k0 - i, o[2 * i + 1]);
+      }
     }
-    if (rb == 0) put(0, o[2 * kPB]);
+    if (rb == 0) put(0, o[2 * kPBMax]);
   }
   if constexpr (TO_LDS) __syncthreads();
 }

@@ -198,6 +198,12 @@ def problem(name):
         lams = np.array([0.45, 0.55, 0.65])
         return dict(n=8192, m=16384, dx=1.0, z=20000.0, lams=lams,
                     n_index=cauchy_index(lams), weights=np.ones(3))
+    if name == "paper":
+        # Table 2's large-area hologram grid: a 32.16 x 21.44 mm DOE at 0.5 um
+        # (rows x columns), padded to 128,640 x 85,760; z = 6 cm
+        lams = np.array([0.5206])
+        return dict(n=(64320, 42880), m=(128640, 85760), dx=0.5, z=60000.0, lams=lams,
+                    n_index=cauchy_index(lams), weights=np.ones(1))
     raise KeyError(name)
 
 
@@ -217,6 +223,11 @@ def heights(name, n=None):
         return h
     if name == "design":
         return uniform_heights(n, seed=4)
+    if name == "paper":
+        # a 2 um design (seeded uniform heights) upsampled 4x by nearest neighbour
+        ny, nx = shape2(n)
+        hc = uniform_heights((ny // 4, nx // 4), seed=16080)
+        return np.repeat(np.repeat(hc, 4, axis=0), 4, axis=1)
     raise KeyError(name)
 
 

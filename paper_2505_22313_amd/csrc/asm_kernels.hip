@@ -746,6 +746,10 @@ __host__ __device__ constexpr int threads_for(int pts) {
 
 struct TablePlan {
   int ax, bx, ay, by;  // Mx = ax * bx columns, My = ay * by rows
+  // pass-C run and threads (0: 16 columns, about 8 points per thread); the
+  // 1005-row tiles of the paper's grid take 8 columns and 512 threads, so two
+  // blocks share a CU and one block's ALU work overlaps the other's traffic
+  int rc = 0, tc = 0;
 };
 constexpr int kTabBase = 100;
 constexpr int kNumTab = 14;
@@ -763,7 +767,7 @@ __host__ __device__ constexpr TablePlan table_plan(int i) {
          : i == 10 ? TablePlan{134, 16, 15, 16}       // 240 x 2144
          : i == 11 ? TablePlan{15, 16, 16, 335}       // 5360 x 240
          : i == 12 ? TablePlan{670, 16, 16, 1005}     // 16080 x 10720
-         : i == 13 ? TablePlan{670, 128, 128, 1005}   // 128640 x 85760: 2^7 3 5 67 x 2^8 5 67
+         : i == 13 ? TablePlan{670, 128, 128, 1005, 8, 512}  // 128640 x 85760: 2^7 3 5 67 x 2^8 5 67
                    : TablePlan{0, 0, 0, 0};
 }
 
@@ -782,7 +786,7 @@ struct Plan {
   static constexpr int AY = POW2 ? 1 << plan_ay(PID) : TP.ay;
   static constexpr int BY = MY / AY;
   static constexpr int RA = cmin(16, BX);  // contiguous run in passes A / A': a 128-byte line
-  static constexpr int RC = cmin(16, MX);  // contiguous run in pass C
+  static constexpr int RC = TP.rc ? TP.rc : cmin(16, MX);  // contiguous run in pass C
   // A / A' tiles (up to 1024 x 16 points, 128 KiB of LDS) run one block of
   // up to 1024 threads per CU
   // (other M: about 8 points per thread, since their mixed-radix stage
@@ -790,7 +794,7 @@ struct Plan {
   static constexpr int TA = round64(cmin(1024, cmax(64, AX * RA / (POW2 ? 16 : 8))));
   static constexpr int TB = !POW2 ? round64(cmin(1024, cmax(64, BX * AY / 8)))
                             : BX * AY > 8192 ? 1024 : threads_for(BX * AY);
-  static constexpr int TC = !POW2 ? round64(cmin(1024, cmax(64, BY * RC / 8)))
+  static constexpr int TC = TP.tc ? TP.tc : !POW2 ? round64(cmin(1024, cmax(64, BY * RC / 8)))
                             : BY * RC > 8192 ? 1024 : threads_for(BY * RC);
   // Twiddles in LDS: omega_M^q = HI[q / S] * LO[q % S] with HI[i] = omega_M^(i S)
   // (= omega_THI^i) and LO[i] = omega_M^i.  Power-of-two M: THI = min(M, 1024),
@@ -1151,14 +1155,17 @@ template <int PID>
 DOP_KERNEL(Plan<PID>::TC) void k_pass_c(KParams p) {
   using P = Plan<PID>;
   constexpr int AX = P::AX, BX = P::BX, AY = P::AY, BY = P::BY, RC = P::RC, T = P::TC;
-  using G = Geo<BY, RC, RC + 1, 1, T, false>;
+  // LDS row stride: one pad element for 16-column tiles; an 8-column tile
+  // goes unpadded so that two blocks fit in a CU's LDS
+  constexpr int SJ = RC >= 16 ? RC + 1 : RC;
+  using G = Geo<BY, RC, SJ, 1, T, false>;
   using FS = FirstStage<G>;
   // A radix-67 stage cannot hand its outputs over in registers: with one, the
   // forward DFT ends in LDS (natural order) and the inverse DFT reads it
   // through a load functor that applies H.
   constexpr bool VIA_LDS = n67(BY) > 0;
   static_assert((size_t)BY * P::PITCH < (1ull << 31), "tile offsets are 32-bit");
-  __shared__ float2 lds[BY * (RC + 1)];
+  __shared__ float2 lds[BY * SJ];
   // only BY-point DFTs run here: their twiddles omega_BY^i, i < BY
   __shared__ float2 twc[BY];
   // a2_eff of the tile's BY frequency rows (and, via LDS, of its RC columns)
@@ -1227,7 +1234,7 @@ DOP_KERNEL(Plan<PID>::TC) void k_pass_c(KParams p) {
       dft_tile_hooked<G, false, false, SRC_REG, SNK_LDS, BY>(lds, twc, NoLoad{}, NoStore{}, hook,
                                                             v, dummy, tid);
       auto ld_h = [&](int kyb, int b) {
-        return cmul(lds[kyb * (RC + 1) + b], transfer(a2row[kyb], a2col[b], p));
+        return cmul(lds[kyb * SJ + b], transfer(a2row[kyb], a2col[b], p));
       };
       dft_tile<G, true, true, SRC_FN, SNK_FN, BY>(lds, twc, ld_h, st, dummy, tid);
     } else {

@@ -102,15 +102,15 @@ def test_serve_many_small_requests_overlap(api):
 
 
 def test_serve_mixed_problem_kinds(api):
-    """Requests that use the band limit, the fused 8x nearest upsampling and
-    grids that are not powers of two, mixed with plain ones: each result is
-    bitwise the same as the request run alone, and a sample matches the
-    oracle."""
+    """Requests that use the band limit, the fused 8x nearest upsampling,
+    grids that are not powers of two and rectangular grids (one with the
+    radix-67 stage), mixed with plain ones: each result is bitwise the same
+    as the request run alone, and a sample matches the oracle."""
     from oracle import upsample as ups
     rng = np.random.default_rng(13)
     reqs = []
-    for i in range(16):
-        kind = i % 4
+    for i in range(18):
+        kind = i % 6
         lams = np.linspace(0.45, 0.65, 1 + i % 3)
         z = float(rng.uniform(500.0, 4000.0))
         if kind == 0:
@@ -122,9 +122,16 @@ def test_serve_mixed_problem_kinds(api):
         elif kind == 2:
             prob = api.Problem(360, 720, 1.0, z, lams, wl.cauchy_index(lams))
             h = wl.uniform_heights(360, seed=300 + i)
-        else:
+        elif kind == 3:
             prob = api.Problem(1500, 3600, 0.5, z, lams, wl.cauchy_index(lams), out_mode="full")
             h = wl.uniform_heights(1500, seed=300 + i)
+        elif kind == 4:
+            prob = api.Problem((200, 1500), (240, 2144), 1.0, z, lams, wl.cauchy_index(lams))
+            h = wl.uniform_heights((200, 1500), seed=300 + i)
+        else:
+            prob = api.Problem((500, 150), (720, 240), 0.5, z, lams, wl.cauchy_index(lams),
+                               out_mode="full")
+            h = wl.uniform_heights((500, 150), seed=300 + i)
         reqs.append((prob, torch.from_numpy(h).cuda(), h))
     alone = [api.psf(hd, prob).clone() for prob, hd, _ in reqs]
     torch.cuda.synchronize()
@@ -141,9 +148,9 @@ def test_serve_mixed_problem_kinds(api):
             assert torch.equal(a, b), f"request {i} differs between alone and mix"
     finally:
         srv.close()
-    for i in range(4):
+    for i in range(6):
         prob, _, h = reqs[i]
         hf = ups.upsample(h, 8, "nearest") if prob.upsample > 1 else h
-        want = oracle.psf(hf, prob.dx, prob.z, prob.m, prob.lambdas, prob.n_index,
+        want = oracle.psf(hf, prob.dx, prob.z, prob.grid_shape, prob.lambdas, prob.n_index,
                           out_mode=prob.out_mode, bandlimit=prob.bandlimit)
         assert np.linalg.norm(alone[i].cpu().numpy() - want) / np.linalg.norm(want) < 2e-5

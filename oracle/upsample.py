@@ -9,8 +9,9 @@ times finer (Sec. 3.2 and its Table 2: 2 um features on a 250 nm grid, i.e.
 by an interpolation kernel: nearest neighbour, which forces box-shaped
 features, or a smooth Lanczos-3 kernel (Getreuer, "Linear Methods for Image
 Interpolation", IPOL 2011).  Both are linear maps U from the coarse map
-(nc x nc) to the fine one (nc*s x nc*s), separable over the two axes:
-h_fine = W hc W^T with a one-axis matrix W of shape (nc*s, nc).
+(ncy x ncx) to the fine one (ncy*s x ncx*s), separable over the two axes:
+h_fine = Wy hc Wx^T with one-axis matrices W of shape (nc*s, nc), one per
+axis length (Wy = Wx on a square design).
 
 * Nearest: fine sample j takes coarse sample floor(j / s).
 * Lanczos-3: fine sample j sits at coarse coordinate u_j = (j + 0.5)/s - 0.5
@@ -19,8 +20,8 @@ h_fine = W hc W^T with a one-axis matrix W of shape (nc*s, nc).
   sinc).  Taps outside [0, nc) are dropped and each row of W is divided by
   the sum of its remaining weights, so a constant map stays constant.
 
-The design gradient needs the adjoint U^T: W^T g W (for nearest, the sum of
-each s x s block).
+The design gradient needs the adjoint U^T: Wy^T g Wx (for nearest, the sum
+of each s x s block).
 
 Parity status: pinned (block repetition, interpolation of coarse samples at
 odd s, partition of unity, reproduction of slowly varying cosines, mirror
@@ -53,15 +54,16 @@ def axis_matrix(nc, s, kind):
 
 
 def upsample(hc, s, kind="nearest"):
-    """h_fine = W hc W^T (float64, (nc*s) x (nc*s))."""
+    """h_fine = Wy hc Wx^T (float64, (ncy*s) x (ncx*s))."""
     hc = np.asarray(hc, dtype=np.float64)
-    w = axis_matrix(hc.shape[0], s, kind)
-    return w @ hc @ w.T
+    wy = axis_matrix(hc.shape[0], s, kind)
+    wx = axis_matrix(hc.shape[1], s, kind)
+    return wy @ hc @ wx.T
 
 
 def upsample_adjoint(g, s, kind="nearest"):
-    """U^T g = W^T g W (float64, nc x nc) for a fine-grid gradient g."""
+    """U^T g = Wy^T g Wx (float64, ncy x ncx) for a fine-grid gradient g."""
     g = np.asarray(g, dtype=np.float64)
-    nc = g.shape[0] // s
-    w = axis_matrix(nc, s, kind)
-    return w.T @ g @ w
+    wy = axis_matrix(g.shape[0] // s, s, kind)
+    wx = axis_matrix(g.shape[1] // s, s, kind)
+    return wy.T @ g @ wx

@@ -580,3 +580,25 @@ def test_psf_lowmem_rows_mode():
     got, total, peak = oracle.psf_lowmem(h, 0.5, 300.0, (96, 160), 0.55, 1.46, block=16, rows=rows)
     assert np.array_equal(got, full[rows])
     assert abs(total - full.sum()) < 1e-12 * full.sum() and peak == full.max()
+
+
+@pytest.mark.parametrize("kind", ["nearest", "lanczos3"])
+def test_rect_upsample_separable_and_adjoint(kind):
+    """Rectangular designs: the upsampling of an outer product a b^T is the
+    outer product of the two one-axis upsamplings (an axis mix-up breaks it),
+    nearest is block repetition, and the adjoint identity holds."""
+    rng = np.random.default_rng(26)
+    s, ncy, ncx = 3, 7, 12
+    a, b = rng.standard_normal(ncy), rng.standard_normal(ncx)
+    fine = ups.upsample(np.outer(a, b), s, kind)
+    assert fine.shape == (ncy * s, ncx * s)
+    fa = ups.upsample(np.outer(a, np.ones(1)), s, kind)[:, 0]
+    fb = ups.upsample(np.outer(np.ones(1), b), s, kind)[0]
+    assert np.allclose(fine, np.outer(fa, fb), rtol=0, atol=1e-13)
+    x = rng.standard_normal((ncy, ncx))
+    g = rng.standard_normal((ncy * s, ncx * s))
+    lhs = np.sum(ups.upsample(x, s, kind) * g)
+    rhs = np.sum(x * ups.upsample_adjoint(g, s, kind))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs) + 1e-12
+    if kind == "nearest":
+        assert np.array_equal(ups.upsample(x, s, kind), np.kron(x, np.ones((s, s))))

@@ -90,7 +90,9 @@ enum { DOP_OP_PROPAGATE = 0, DOP_OP_PSF = 1, DOP_OP_PSF_BACKWARD = 2 };
 
 /*
  * Problem description (paper Sec. 3.1: grid, pitch, wavelengths, index,
- * distance, padding).  Host arrays are read during the call only.
+ * distance, padding).  Host arrays are read during the call only.  In the
+ * calls below, "N x N" stands for the DOE's ny rows x n columns and "M x M"
+ * for the grid's my rows x m columns.
  */
 typedef struct {
   int32_t n;             /* DOE columns (n x n when ny = 0), 1 <= n <= m     */
@@ -147,10 +149,10 @@ dop_status dop_context_destroy(dop_context *ctx);
 
 /*
  * Workspace bytes an operation needs for `prob` (op = DOP_OP_*): one M x M
- * c64 field stored with a row pitch of M + 16 elements (8 M (M + 16) bytes),
- * plus, for DOP_OP_PSF_BACKWARD with upsample >= 2, an n x n float32
- * fine-grid gradient (starting at the next 256-byte boundary).  Pure host
- * call.
+ * c64 field stored with a row pitch of m + 16 elements (8 my (m + 16)
+ * bytes), plus, for DOP_OP_PSF_BACKWARD with upsample >= 2, an ny x n
+ * float32 fine-grid gradient (starting at the next 256-byte boundary).  Pure
+ * host call.
  */
 dop_status dop_workspace_size(const dop_context *ctx, const dop_problem *prob,
                               int op, size_t *bytes);
@@ -219,6 +221,17 @@ dop_status dop_upsample(dop_context *ctx, int kind, int nc, int s,
 dop_status dop_upsample_adjoint(dop_context *ctx, int kind, int nc, int s,
                                 const float *grad_fine, float *grad_coarse,
                                 void *stream);
+
+/* The same two maps for a rectangular design of ncy rows and ncx columns
+ * (each axis has its own W, fine = Wy coarse Wx^T, grad_coarse = Wy^T
+ * grad_fine Wx; the paper's large-area design is 16,080 x 10,720 samples):
+ * coarse ncy x ncx, fine (ncy s) x (ncx s), the same limits per axis.
+ * dop_upsample and dop_upsample_adjoint are these with ncy = ncx = nc. */
+dop_status dop_upsample_rect(dop_context *ctx, int kind, int ncy, int ncx, int s,
+                             const float *coarse, float *fine, void *stream);
+dop_status dop_upsample_adjoint_rect(dop_context *ctx, int kind, int ncy, int ncx,
+                                     int s, const float *grad_fine,
+                                     float *grad_coarse, void *stream);
 
 /* ------------------------------------------------------------------------
  * Per-pass timing.  While enabled, every wavelength's five passes are

@@ -114,6 +114,10 @@ _SIGNATURES = {
     "dop_upsample": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP]),
     "dop_upsample_adjoint": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP,
                                             _VP]),
+    "dop_upsample_rect": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, _VP, _VP, _VP]),
+    "dop_upsample_adjoint_rect": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                 ctypes.c_int, _VP, _VP, _VP]),
     "dop_profile_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
     "dop_profile_read": (ctypes.c_int, [_VP, ctypes.POINTER(DopPassProfile), ctypes.c_int,
                                         ctypes.POINTER(ctypes.c_int)]),

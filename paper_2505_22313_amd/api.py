@@ -279,36 +279,42 @@ UPSAMPLE_KINDS = {"nearest": L.DOP_UPSAMPLE_NEAREST, "lanczos3": L.DOP_UPSAMPLE_
 
 
 def upsample(coarse, s, kind="nearest", ctx=None, out=None):
-    """Super-resolved front end: the (nc s) x (nc s) map W coarse W^T of an
-    nc x nc float32 design (nearest or Lanczos-3 interpolation)."""
+    """Super-resolved front end: the (ncy s) x (ncx s) map Wy coarse Wx^T of
+    an ncy x ncx float32 design (nearest or Lanczos-3 interpolation)."""
     ctx = ctx or default_context(coarse.device.index)
     dev = ctx.device
-    nc = coarse.shape[0]
-    _need(coarse, "coarse", torch.float32, (nc, nc), dev)
-    nf = nc * int(s)
+    if coarse.dim() != 2:
+        raise ValueError("coarse must be a 2-D map")
+    ncy, ncx = int(coarse.shape[0]), int(coarse.shape[1])
+    _need(coarse, "coarse", torch.float32, (ncy, ncx), dev)
+    fine = (ncy * int(s), ncx * int(s))
     if out is None:
-        out = torch.empty((nf, nf), dtype=torch.float32, device=coarse.device)
-    _need(out, "out", torch.float32, (nf, nf), dev)
-    check(lib().dop_upsample(ctx.handle, UPSAMPLE_KINDS[kind], nc, int(s), _ptr(coarse), _ptr(out),
-                             ctypes.c_void_p(_stream_handle(dev))), "dop_upsample")
+        out = torch.empty(fine, dtype=torch.float32, device=coarse.device)
+    _need(out, "out", torch.float32, fine, dev)
+    check(lib().dop_upsample_rect(ctx.handle, UPSAMPLE_KINDS[kind], ncy, ncx, int(s),
+                                  _ptr(coarse), _ptr(out), ctypes.c_void_p(_stream_handle(dev))),
+          "dop_upsample_rect")
     return out
 
 
 def upsample_adjoint(grad_fine, s, kind="nearest", ctx=None, out=None):
-    """W^T grad_fine W: a fine-grid gradient carried back to the design."""
+    """Wy^T grad_fine Wx: a fine-grid gradient carried back to the design."""
     ctx = ctx or default_context(grad_fine.device.index)
     dev = ctx.device
-    nf = grad_fine.shape[0]
-    if nf % int(s):
-        raise ValueError(f"fine size {nf} is not a multiple of {s}")
-    _need(grad_fine, "grad_fine", torch.float32, (nf, nf), dev)
-    nc = nf // int(s)
+    if grad_fine.dim() != 2:
+        raise ValueError("grad_fine must be a 2-D map")
+    nfy, nfx = int(grad_fine.shape[0]), int(grad_fine.shape[1])
+    if nfy % int(s) or nfx % int(s):
+        raise ValueError(f"fine size {nfy} x {nfx} is not a multiple of {s}")
+    _need(grad_fine, "grad_fine", torch.float32, (nfy, nfx), dev)
+    ncy, ncx = nfy // int(s), nfx // int(s)
     if out is None:
-        out = torch.empty((nc, nc), dtype=torch.float32, device=grad_fine.device)
-    _need(out, "out", torch.float32, (nc, nc), dev)
-    check(lib().dop_upsample_adjoint(ctx.handle, UPSAMPLE_KINDS[kind], nc, int(s),
-                                     _ptr(grad_fine), _ptr(out),
-                                     ctypes.c_void_p(_stream_handle(dev))), "dop_upsample_adjoint")
+        out = torch.empty((ncy, ncx), dtype=torch.float32, device=grad_fine.device)
+    _need(out, "out", torch.float32, (ncy, ncx), dev)
+    check(lib().dop_upsample_adjoint_rect(ctx.handle, UPSAMPLE_KINDS[kind], ncy, ncx, int(s),
+                                          _ptr(grad_fine), _ptr(out),
+                                          ctypes.c_void_p(_stream_handle(dev))),
+          "dop_upsample_adjoint_rect")
     return out
 
 

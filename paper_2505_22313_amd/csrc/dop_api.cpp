@@ -461,55 +461,68 @@ dop_status dop_psf_backward(dop_context *ctx, const dop_problem *prob, const flo
     if (s != DOP_OK) return s;
   }
   if (up > 1) {
-    const hipError_t e = launch_upsample_nearest_adjoint(doe_rows(prob) / up, prob->n / up, up,
-                                                         grad_fine, grad_h,
-                                                         static_cast<hipStream_t>(stream));
+    const hipError_t e = launch_upsample_adjoint(DOP_UPSAMPLE_NEAREST, doe_rows(prob) / up,
+                                                 prob->n / up, up, grad_fine, grad_h,
+                                                 static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
       return fail(DOP_ERR_DEVICE, "upsample adjoint launch failed: %s", hipGetErrorString(e));
   }
   return DOP_OK;
 }
 
-static dop_status check_upsample_args(const dop_context *ctx, int kind, int nc, int s,
+static dop_status check_upsample_args(const dop_context *ctx, int kind, int ncy, int ncx, int s,
                                       const void *in, const void *out) {
   if (!ctx) return fail(DOP_ERR_INVALID_ARG, "context is NULL");
   if (kind != DOP_UPSAMPLE_NEAREST && kind != DOP_UPSAMPLE_LANCZOS3)
     return fail(DOP_ERR_INVALID_ARG, "unknown upsample kind %d", kind);
-  if (nc < 1) return fail(DOP_ERR_INVALID_ARG, "nc must be >= 1 (got %d)", nc);
+  if (ncy < 1 || ncx < 1)
+    return fail(DOP_ERR_INVALID_ARG, "coarse grid must be at least 1 x 1 (got %d x %d)", ncy, ncx);
   if (s < 1 || s > DOP_MAX_UPSAMPLE)
     return fail(DOP_ERR_UNSUPPORTED, "factor must be in [1, %d] (got %d)", DOP_MAX_UPSAMPLE, s);
-  if ((long long)nc * s > DOP_MAX_M)
-    return fail(DOP_ERR_UNSUPPORTED, "nc * s = %lld exceeds %d", (long long)nc * s, DOP_MAX_M);
+  if ((long long)ncy * s > DOP_MAX_M || (long long)ncx * s > DOP_MAX_M)
+    return fail(DOP_ERR_UNSUPPORTED, "fine grid %lld x %lld exceeds %d", (long long)ncy * s,
+                (long long)ncx * s, DOP_MAX_M);
   if (!in || !out) return fail(DOP_ERR_INVALID_ARG, "arrays must not be NULL");
   if (!aligned(in, 4) || !aligned(out, 4))
     return fail(DOP_ERR_INVALID_ARG, "float arrays must be 4-byte aligned");
-  const size_t nf = (size_t)nc * s;
   const char *a = static_cast<const char *>(in), *b = static_cast<const char *>(out);
-  const size_t na = (size_t)nc * nc * sizeof(float), nb = nf * nf * sizeof(float);
+  const size_t na = (size_t)ncy * ncx * sizeof(float);
+  const size_t nb = (size_t)ncy * s * ((size_t)ncx * s) * sizeof(float);
   if (a < b + nb && b < a + na) return fail(DOP_ERR_INVALID_ARG, "input and output overlap");
   return check_ctx_device(ctx);
 }
 
-dop_status dop_upsample(dop_context *ctx, int kind, int nc, int s, const float *coarse, float *fine,
-                        void *stream) {
+dop_status dop_upsample_rect(dop_context *ctx, int kind, int ncy, int ncx, int s,
+                             const float *coarse, float *fine, void *stream) {
   clear_error();
-  const dop_status st = check_upsample_args(ctx, kind, nc, s, coarse, fine);
+  const dop_status st = check_upsample_args(ctx, kind, ncy, ncx, s, coarse, fine);
   if (st != DOP_OK) return st;
-  const hipError_t e = launch_upsample(kind, nc, s, coarse, fine, static_cast<hipStream_t>(stream));
+  const hipError_t e =
+      launch_upsample(kind, ncy, ncx, s, coarse, fine, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(DOP_ERR_DEVICE, "upsample launch failed: %s", hipGetErrorString(e));
   return DOP_OK;
 }
 
-dop_status dop_upsample_adjoint(dop_context *ctx, int kind, int nc, int s, const float *grad_fine,
-                                float *grad_coarse, void *stream) {
+dop_status dop_upsample_adjoint_rect(dop_context *ctx, int kind, int ncy, int ncx, int s,
+                                     const float *grad_fine, float *grad_coarse, void *stream) {
   clear_error();
-  const dop_status st = check_upsample_args(ctx, kind, nc, s, grad_coarse, grad_fine);
+  const dop_status st = check_upsample_args(ctx, kind, ncy, ncx, s, grad_coarse, grad_fine);
   if (st != DOP_OK) return st;
-  const hipError_t e = launch_upsample_adjoint(kind, nc, s, grad_fine, grad_coarse,
+  const hipError_t e = launch_upsample_adjoint(kind, ncy, ncx, s, grad_fine, grad_coarse,
                                                static_cast<hipStream_t>(stream));
   if (e != hipSuccess)
     return fail(DOP_ERR_DEVICE, "upsample adjoint launch failed: %s", hipGetErrorString(e));
   return DOP_OK;
+}
+
+dop_status dop_upsample(dop_context *ctx, int kind, int nc, int s, const float *coarse, float *fine,
+                        void *stream) {
+  return dop_upsample_rect(ctx, kind, nc, nc, s, coarse, fine, stream);
+}
+
+dop_status dop_upsample_adjoint(dop_context *ctx, int kind, int nc, int s, const float *grad_fine,
+                                float *grad_coarse, void *stream) {
+  return dop_upsample_adjoint_rect(ctx, kind, nc, nc, s, grad_fine, grad_coarse, stream);
 }
 
 }  // extern "C"

@@ -97,16 +97,13 @@ struct PlanInfo {
 };
 bool plan_info(int plan, PlanInfo *out);
 
-// Super-resolved front end: fine = W coarse W^T and its adjoint (kind 0:
-// nearest, 1: Lanczos-3; see dop_upsample).  Arguments already validated.
-hipError_t launch_upsample(int kind, int nc, int s, const float *coarse, float *fine,
+// Super-resolved front end: fine = Wy coarse Wx^T and its adjoint for a
+// coarse design of ncy rows and ncx columns (kind 0: nearest, 1: Lanczos-3;
+// see dop_upsample).  Arguments already validated.
+hipError_t launch_upsample(int kind, int ncy, int ncx, int s, const float *coarse, float *fine,
                            hipStream_t stream);
-hipError_t launch_upsample_adjoint(int kind, int nc, int s, const float *grad_fine,
+hipError_t launch_upsample_adjoint(int kind, int ncy, int ncx, int s, const float *grad_fine,
                                    float *grad_coarse, hipStream_t stream);
-// Nearest-neighbour adjoint (s x s block sums) of a rectangular coarse grid of
-// ncy rows and ncx columns.
-hipError_t launch_upsample_nearest_adjoint(int ncy, int ncx, int s, const float *grad_fine,
-                                           float *grad_coarse, hipStream_t stream);
 
 }  // namespace dop
 

@@ -2,7 +2,9 @@
 // grid by a separable interpolation kernel (paper Sec. 3.2, Table 2), and the
 // design gradient is carried back by the adjoint map.
 //
-//   fine = W coarse W^T,   grad_coarse = W^T grad_fine W,   W: (nc s) x nc.
+//   fine = Wy coarse Wx^T,   grad_coarse = Wy^T grad_fine Wx,   W: (nc s) x nc
+//
+// for a coarse design of ncy rows and ncx columns (each axis has its own W).
 //
 // Nearest: W[j][i] = [i == j / s].  Lanczos-3: fine sample j sits at coarse
 // coordinate u_j = (j + 0.5)/s - 0.5 and takes the six coarse samples
@@ -88,13 +90,14 @@ DEV int lanczos_taps(int j, int s, int nc, const TapTable &tt, float *w) {
 // ---------------------------------------------------------------------------
 // Nearest neighbour.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_up_nearest(int nc, int s, const float *__restrict__ in,
+__global__ __launch_bounds__(256) void k_up_nearest(int ncy, int ncx, int s,
+                                                    const float *__restrict__ in,
                                                     float *__restrict__ out) {
-  const int nf = nc * s;
-  for (int y = blockIdx.y; y < nf; y += gridDim.y) {
-    const float *src = in + (size_t)(y / s) * nc;
-    float *dst = out + (size_t)y * nf;
-    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < nf; x += gridDim.x * blockDim.x)
+  const int nfy = ncy * s, nfx = ncx * s;
+  for (int y = blockIdx.y; y < nfy; y += gridDim.y) {
+    const float *src = in + (size_t)(y / s) * ncx;
+    float *dst = out + (size_t)y * nfx;
+    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < nfx; x += gridDim.x * blockDim.x)
       dst[x] = src[x / s];
   }
 }
@@ -125,9 +128,10 @@ __global__ __launch_bounds__(256) void k_up_nearest_adj(int ncy, int ncx, int s,
 constexpr int kUpTile = 64;
 constexpr int kUpPatch = kUpTile + 6;
 
-__global__ __launch_bounds__(256) void k_up_lanczos(int nc, int s, const float *__restrict__ in,
+__global__ __launch_bounds__(256) void k_up_lanczos(int ncy, int ncx, int s,
+                                                    const float *__restrict__ in,
                                                     float *__restrict__ out) {
-  const int nf = nc * s;
+  const int nfy = ncy * s, nfx = ncx * s;
   __shared__ float rw[kUpTile][6], cw[kUpTile][6];
   __shared__ int rs[kUpTile], cs[kUpTile];
   __shared__ float patch[kUpPatch][kUpPatch + 1];
@@ -140,10 +144,10 @@ __global__ __launch_bounds__(256) void k_up_lanczos(int nc, int s, const float *
   // taps of every row and column of the tile (clamped to the grid: rows past
   // the edge repeat the last one and are not written)
   if (tid < kUpTile) {
-    rs[tid] = lanczos_taps(min(fy0 + tid, nf - 1), s, nc, tt, rw[tid]);
+    rs[tid] = lanczos_taps(min(fy0 + tid, nfy - 1), s, ncy, tt, rw[tid]);
   } else if (tid < 2 * kUpTile) {
     const int c = tid - kUpTile;
-    cs[c] = lanczos_taps(min(fx0 + c, nf - 1), s, nc, tt, cw[c]);
+    cs[c] = lanczos_taps(min(fx0 + c, nfx - 1), s, ncx, tt, cw[c]);
   }
   __syncthreads();
   const int cy0 = rs[0], cx0 = cs[0];
@@ -152,7 +156,7 @@ __global__ __launch_bounds__(256) void k_up_lanczos(int nc, int s, const float *
   for (int e = tid; e < pr * pc; e += blockDim.x) {
     const int r = e / pc, c = e - (e / pc) * pc;
     const int gy = cy0 + r, gx = cx0 + c;
-    patch[r][c] = (gy >= 0 && gy < nc && gx >= 0 && gx < nc) ? in[(size_t)gy * nc + gx] : 0.f;
+    patch[r][c] = (gy >= 0 && gy < ncy && gx >= 0 && gx < ncx) ? in[(size_t)gy * ncx + gx] : 0.f;
   }
   __syncthreads();
   // along y: vert[r][c] = sum_t rw[r][t] patch[rs[r] - cy0 + t][c]
@@ -169,12 +173,12 @@ __global__ __launch_bounds__(256) void k_up_lanczos(int nc, int s, const float *
   for (int e = tid; e < kUpTile * kUpTile; e += blockDim.x) {
     const int r = e / kUpTile, c = e % kUpTile;
     const int fy = fy0 + r, fx = fx0 + c;
-    if (fy >= nf || fx >= nf) continue;
+    if (fy >= nfy || fx >= nfx) continue;
     const int o = cs[c] - cx0;
     float a = 0.f;
 #pragma unroll
     for (int t = 0; t < 6; ++t) a += cw[c][t] * vert[r][o + t];
-    out[(size_t)fy * nf + fx] = a;
+    out[(size_t)fy * nfx + fx] = a;
   }
 }
 
@@ -195,12 +199,12 @@ DEV int fine_lo(int i, int s) { return s * (i - 3) - 1; }
 DEV int fine_hi(int i, int s) { return s * (i + 3) + s; }
 
 template <int SMAX>
-__global__ __launch_bounds__(kAdjThreads) void k_up_lanczos_adj(int nc, int s,
+__global__ __launch_bounds__(kAdjThreads) void k_up_lanczos_adj(int ncy, int ncx, int s,
                                                                 const float *__restrict__ g,
                                                                 float *__restrict__ out) {
   constexpr int SPAN = SMAX * (kAdjTile + 6) + 2;
   constexpr int PF = (kAdjChunk * SPAN + kAdjThreads - 1) / kAdjThreads;
-  const int nf = nc * s;
+  const int nfy = ncy * s, nfx = ncx * s;
   __shared__ TapTable tt;
   __shared__ float rw[SPAN][6], cw[SPAN][6];
   __shared__ int rs[SPAN], cs[SPAN];
@@ -208,13 +212,13 @@ __global__ __launch_bounds__(kAdjThreads) void k_up_lanczos_adj(int nc, int s,
   __shared__ float chunk[kAdjChunk][SPAN + 1];
   const int i0 = blockIdx.y * kAdjTile, k0 = blockIdx.x * kAdjTile;
   const int tid = threadIdx.x;
-  const int jlo = max(0, fine_lo(i0, s)), jhi = min(nf - 1, fine_hi(i0 + kAdjTile - 1, s));
-  const int llo = max(0, fine_lo(k0, s)), lhi = min(nf - 1, fine_hi(k0 + kAdjTile - 1, s));
+  const int jlo = max(0, fine_lo(i0, s)), jhi = min(nfy - 1, fine_hi(i0 + kAdjTile - 1, s));
+  const int llo = max(0, fine_lo(k0, s)), lhi = min(nfx - 1, fine_hi(k0 + kAdjTile - 1, s));
   const int nj = jhi - jlo + 1, nl = lhi - llo + 1;
   tap_table_fill(tt, s);
   __syncthreads();
-  for (int e = tid; e < nj; e += kAdjThreads) rs[e] = lanczos_taps(jlo + e, s, nc, tt, rw[e]);
-  for (int e = tid; e < nl; e += kAdjThreads) cs[e] = lanczos_taps(llo + e, s, nc, tt, cw[e]);
+  for (int e = tid; e < nj; e += kAdjThreads) rs[e] = lanczos_taps(jlo + e, s, ncy, tt, rw[e]);
+  for (int e = tid; e < nl; e += kAdjThreads) cs[e] = lanczos_taps(llo + e, s, ncx, tt, cw[e]);
   float nxt[PF];
   auto load_chunk = [&](int c0) {
     const int rows = min(kAdjChunk, nj - c0);
@@ -222,7 +226,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_up_lanczos_adj(int nc, int s,
     for (int q = 0; q < PF; ++q) {
       const int e = tid + q * kAdjThreads;
       const int r = e / nl, c = e - (e / nl) * nl;
-      nxt[q] = r < rows ? g[(size_t)(jlo + c0 + r) * nf + llo + c] : 0.f;
+      nxt[q] = r < rows ? g[(size_t)(jlo + c0 + r) * nfx + llo + c] : 0.f;
     }
   };
   const int kk = tid % kAdjTile;  // coarse column of this thread
@@ -252,14 +256,14 @@ __global__ __launch_bounds__(kAdjThreads) void k_up_lanczos_adj(int nc, int s,
   }
   __syncthreads();
   const int i = i0 + tid / kAdjTile;
-  if (i < nc && k < nc) {
+  if (i < ncy && k < ncx) {
     const int rlo = max(0, fine_lo(i, s) - jlo), rhi = min(nj - 1, fine_hi(i, s) - jlo);
     float a = 0.f;
     for (int r = rlo; r <= rhi; ++r) {
       const int t = i - rs[r];
       if (t >= 0 && t < 6) a += rw[r][t] * hsum[r][kk];
     }
-    out[(size_t)i * nc + k] = a;
+    out[(size_t)i * ncx + k] = a;
   }
 }
 
@@ -267,39 +271,33 @@ unsigned cdiv(int a, int b) { return (unsigned)((a + b - 1) / b); }
 
 }  // namespace
 
-hipError_t launch_upsample(int kind, int nc, int s, const float *coarse, float *fine,
+hipError_t launch_upsample(int kind, int ncy, int ncx, int s, const float *coarse, float *fine,
                            hipStream_t stream) {
-  const int nf = nc * s;
+  const int nfy = ncy * s, nfx = ncx * s;
   if (kind == 0) {
-    const dim3 grid(cdiv(nf, 256) < 64 ? cdiv(nf, 256) : 64, nf < 4096 ? nf : 4096);
-    hipLaunchKernelGGL(k_up_nearest, grid, dim3(256), 0, stream, nc, s, coarse, fine);
+    const dim3 grid(cdiv(nfx, 256) < 64 ? cdiv(nfx, 256) : 64, nfy < 4096 ? nfy : 4096);
+    hipLaunchKernelGGL(k_up_nearest, grid, dim3(256), 0, stream, ncy, ncx, s, coarse, fine);
   } else {
-    const dim3 grid(cdiv(nf, kUpTile), cdiv(nf, kUpTile));
-    hipLaunchKernelGGL(k_up_lanczos, grid, dim3(256), 0, stream, nc, s, coarse, fine);
+    const dim3 grid(cdiv(nfx, kUpTile), cdiv(nfy, kUpTile));
+    hipLaunchKernelGGL(k_up_lanczos, grid, dim3(256), 0, stream, ncy, ncx, s, coarse, fine);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_upsample_nearest_adjoint(int ncy, int ncx, int s, const float *grad_fine,
-                                           float *grad_coarse, hipStream_t stream) {
-  const dim3 grid(cdiv(ncx, 256) < 64 ? cdiv(ncx, 256) : 64, ncy < 4096 ? ncy : 4096);
-  hipLaunchKernelGGL(k_up_nearest_adj, grid, dim3(256), 0, stream, ncy, ncx, s, grad_fine,
-                     grad_coarse);
-  return hipGetLastError();
-}
-
-hipError_t launch_upsample_adjoint(int kind, int nc, int s, const float *grad_fine,
+hipError_t launch_upsample_adjoint(int kind, int ncy, int ncx, int s, const float *grad_fine,
                                    float *grad_coarse, hipStream_t stream) {
   if (kind == 0) {
-    return launch_upsample_nearest_adjoint(nc, nc, s, grad_fine, grad_coarse, stream);
+    const dim3 grid(cdiv(ncx, 256) < 64 ? cdiv(ncx, 256) : 64, ncy < 4096 ? ncy : 4096);
+    hipLaunchKernelGGL(k_up_nearest_adj, grid, dim3(256), 0, stream, ncy, ncx, s, grad_fine,
+                       grad_coarse);
   } else {
-    const dim3 grid(cdiv(nc, kAdjTile), cdiv(nc, kAdjTile));
+    const dim3 grid(cdiv(ncx, kAdjTile), cdiv(ncy, kAdjTile));
     if (s <= 8)
-      hipLaunchKernelGGL(k_up_lanczos_adj<8>, grid, dim3(kAdjThreads), 0, stream, nc, s, grad_fine,
-                         grad_coarse);
-    else
-      hipLaunchKernelGGL(k_up_lanczos_adj<kUpMaxS>, grid, dim3(kAdjThreads), 0, stream, nc, s,
+      hipLaunchKernelGGL(k_up_lanczos_adj<8>, grid, dim3(kAdjThreads), 0, stream, ncy, ncx, s,
                          grad_fine, grad_coarse);
+    else
+      hipLaunchKernelGGL(k_up_lanczos_adj<kUpMaxS>, grid, dim3(kAdjThreads), 0, stream, ncy, ncx,
+                         s, grad_fine, grad_coarse);
   }
   return hipGetLastError();
 }

@@ -369,6 +369,34 @@ def test_upsample_argument_checks(args, code):
     assert st == code, L.last_error()
 
 
+@pytest.mark.parametrize("args,code", [
+    ((1, 0, 64, 8, 256, 1 << 20), L.DOP_ERR_INVALID_ARG),        # ncy < 1
+    ((1, 64, 0, 8, 256, 1 << 20), L.DOP_ERR_INVALID_ARG),        # ncx < 1
+    ((1, 16384, 8, 16, 256, 1 << 30), L.DOP_ERR_UNSUPPORTED),    # ncy s > 131072
+    ((1, 8, 16384, 16, 256, 1 << 30), L.DOP_ERR_UNSUPPORTED),    # ncx s > 131072
+    # a 100 x 10 design is 4,000 bytes, its 4x fine map 400 x 40 floats = 64,000 bytes
+    ((1, 100, 10, 4, 1 << 20, (1 << 20) + 2000), L.DOP_ERR_INVALID_ARG),   # overlap
+    ((1, 100, 10, 4, 1 << 20, (1 << 20) - 60000), L.DOP_ERR_INVALID_ARG),  # overlap
+])
+def test_upsample_rect_argument_checks(args, code):
+    """The rectangular entry points check each axis; a stand-in context is
+    never dereferenced because a check fails first."""
+    kind, ncy, ncx, s, a, b = args
+    ctx = ctypes.c_void_p(64)
+    st = lib().dop_upsample_rect(ctx, kind, ncy, ncx, s, ctypes.c_void_p(a), ctypes.c_void_p(b),
+                                 None)
+    assert st == code, L.last_error()
+    st = lib().dop_upsample_adjoint_rect(ctx, kind, ncy, ncx, s, ctypes.c_void_p(b),
+                                         ctypes.c_void_p(a), None)
+    assert st == code, L.last_error()
+
+
+def test_upsample_rect_null_context_first():
+    st = lib().dop_upsample_rect(None, 1, 10, 20, 4, ctypes.c_void_p(256), ctypes.c_void_p(1 << 20),
+                                 None)
+    assert st == L.DOP_ERR_INVALID_ARG and "context" in L.last_error()
+
+
 @pytest.mark.parametrize("policy", ["fifo", "size_aware"])
 def test_serve_size_aware_policy(policy):
     """Mock service time ~ work (n_lambda m^2).  Under the size-aware policy a

@@ -141,3 +141,49 @@ def test_lanczos_design_gradient_through_autograd(api):
     gpsf = 2.0 * (p - target) / (n * n)
     want = ups.upsample_adjoint(oracle.psf_backward(hf, dx, z, m, lams, nidx, gpsf), s, "lanczos3")
     assert rel(hcd.grad.cpu().numpy(), want) < GRAD_TOL
+
+
+# (ncy, ncx, s): rectangular designs, one-sample axes, fine axes that are not
+# a multiple of the 64-pixel tile
+RECT_SIZES = [(1, 5, 16), (5, 37, 3), (37, 8, 8), (100, 70, 2), (64, 130, 5), (9, 200, 1)]
+
+
+@pytest.mark.parametrize("ncy,ncx,s", RECT_SIZES)
+@pytest.mark.parametrize("kind", ["nearest", "lanczos3"])
+def test_rect_upsample_and_adjoint_match_oracle(api, ncy, ncx, s, kind):
+    rng = np.random.default_rng(ncy * 131 + ncx * 7 + s)
+    hc = rng.uniform(0.0, 1.2, (ncy, ncx)).astype(np.float32)
+    got = api.upsample(dev(hc), s, kind).cpu().numpy()
+    want = ups.upsample(hc, s, kind)
+    assert got.shape == (ncy * s, ncx * s)
+    if kind == "nearest":
+        assert np.array_equal(got, want.astype(np.float32))
+    else:
+        assert rel(got, want) < 1e-6
+    g = rng.standard_normal((ncy * s, ncx * s)).astype(np.float32)
+    got_a = api.upsample_adjoint(dev(g), s, kind).cpu().numpy()
+    assert got_a.shape == (ncy, ncx)
+    assert rel(got_a, ups.upsample_adjoint(g, s, kind)) < 1e-5
+
+
+def test_rect_lanczos_design_gradient_through_autograd(api):
+    """A 60 x 30 design, Lanczos-3 at 4x, on the 720 x 240 grid: the gradient
+    of a PSF loss with respect to the coarse design equals the oracle chain."""
+    ncy, ncx, s, my, mx, dx, z = 60, 30, 4, 720, 240, 0.5, 600.0
+    ny, nx = ncy * s, ncx * s
+    lams = np.array([0.5, 0.62])
+    nidx = wl.cauchy_index(lams)
+    rng = np.random.default_rng(64)
+    hc = rng.uniform(0.0, 1.2, (ncy, ncx)).astype(np.float32)
+    target = wl.gaussian_target((ny, nx), 3.0, total=2.0 * ny * nx)
+    prob = api.Problem((ny, nx), (my, mx), dx, z, lams, nidx)
+    hcd = dev(hc).requires_grad_(True)
+    h = api.DopUpsample.apply(hcd, s, "lanczos3")
+    loss = torch.mean((api.DopPSF.apply(h, prob) - dev(target)) ** 2)
+    loss.backward()
+    hf = ups.upsample(hc, s, "lanczos3")
+    p = oracle.psf(hf, dx, z, (my, mx), lams, nidx)
+    gpsf = 2.0 * (p - target) / (ny * nx)
+    want = ups.upsample_adjoint(oracle.psf_backward(hf, dx, z, (my, mx), lams, nidx, gpsf), s,
+                                "lanczos3")
+    assert rel(hcd.grad.cpu().numpy(), want) < GRAD_TOL

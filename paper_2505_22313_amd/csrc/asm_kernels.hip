@@ -2,9 +2,10 @@
 // DOE, Eq. (1)-(4) of Wei et al., "Large-Area Fabrication-Aware Computational
 // Diffractive Optics" (Sec. 3.1).
 //
-// One wavelength = five passes over an M x M complex64 field held in HBM.
-// Each axis index is split into two digits,
-//     x = BX * xa + xb,   y = BY * ya + yb      (M = AX * BX = AY * BY),
+// One wavelength = five passes over an My x Mx complex64 field held in HBM
+// (square, or rectangular as the paper's 128,640 x 85,760 grid).  Each axis
+// index is split into two digits,
+//     x = BX * xa + xb,   y = BY * ya + yb      (Mx = AX * BX, My = AY * BY),
 // and the 2-D FFT is the row-column decomposition of the paper's Sec. 4.1
 // carried one step further: the 1-D transforms along x and y are themselves
 // four-step (digit) transforms.  Forward transforms work in place and leave
@@ -28,8 +29,10 @@
 // same result shifted by p0 = (M - N)/2, applied when writing a full plane.
 //
 // Within a pass each tile lives in LDS and its DFTs run as Stockham radix
-// 16/8/4 stages in registers.  Inner twiddles and four-step twiddles come
-// from one FP64-generated complex64 table of exp(-2 pi i j / 65536).
+// 16/8/4 (and 3, 5, 9, 15) stages in registers, or a radix-67 stage through
+// LDS.  Inner twiddles and four-step twiddles come from one FP64-generated
+// complex64 table of exp(-2 pi i j / 2^17) on power-of-two grids, and are
+// generated per block in FP64 on the others.
 
 #include <hip/hip_runtime.h>
 #include <math.h>

@@ -1,0 +1,92 @@
+"""Seeded random problems on every small plan (square and rectangular, powers
+of two, 3/5 factors and the prime 67), through the C ABI, against the FP64
+oracle.  Each case draws its DOE size per axis (ragged, up to no padding),
+pitch and wavelengths (evanescent bins included), the sign of z, the output
+mode, the band limit, weights, an amplitude mask and the fused nearest
+upsampling where the DOE size allows it; the PSF is compared element by
+element (rel-L2 <= 2e-5) and, for crop output, the gradient (<= 1e-4).
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import asm
+from oracle import upsample as ups
+from paper_2505_22313_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+asm.WORKERS = min(16, os.cpu_count() or 1)
+
+# (rows, columns) of the grids drawn from
+GRIDS = [(16, 16), (64, 64), (256, 256), (1024, 1024), (240, 240), (720, 720), (1440, 1440),
+         (2144, 2144), (720, 240), (512, 2048), (240, 2144), (5360, 240)]
+CASES = 36
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_22313_amd import api as _api
+    yield _api
+    torch.cuda.empty_cache()
+
+
+def draw(seed):
+    rng = np.random.default_rng(seed)
+    my, mx = GRIDS[seed % len(GRIDS)]
+    up = int(rng.choice([1, 1, 2, 4]))
+    ny = int(rng.integers(1, my + 1))
+    nx = int(rng.integers(1, mx + 1))
+    if rng.random() < 0.2:
+        ny, nx = my, mx  # no padding
+    ny, nx = max(up, ny - ny % up), max(up, nx - nx % up)
+    k = int(rng.integers(1, 4))
+    lams = np.sort(rng.uniform(0.4, 0.7, k))
+    return dict(my=my, mx=mx, ny=ny, nx=nx, up=up, lams=lams,
+                dx=float(rng.choice([0.25, 0.5, 1.0])),
+                z=float(rng.uniform(50.0, 3000.0) * rng.choice([-1, 1])),
+                full=bool(rng.random() < 0.3), bandlimit=bool(rng.random() < 0.3),
+                weights=rng.uniform(0.5, 2.0, k).astype(np.float32),
+                amp=bool(rng.random() < 0.4), seed=seed)
+
+
+@pytest.mark.parametrize("seed", range(CASES))
+def test_random_problem_matches_oracle(api, seed):
+    c = draw(seed)
+    print(f"case {seed}: grid {c['my']}x{c['mx']} doe {c['ny']}x{c['nx']} up {c['up']} "
+          f"k {len(c['lams'])} z {c['z']:.0f} full {c['full']} bl {c['bandlimit']}", flush=True)
+    rng = np.random.default_rng(1000 + seed)
+    ny, nx, up = c["ny"], c["nx"], c["up"]
+    hc = rng.uniform(0.0, 1.2, (ny // up, nx // up)).astype(np.float32)
+    hf = ups.upsample(hc, up, "nearest") if up > 1 else hc.astype(np.float64)
+    amp = rng.uniform(0.3, 1.0, (ny, nx)).astype(np.float32) if c["amp"] else None
+    nidx = wl.cauchy_index(c["lams"])
+    mode = "full" if c["full"] else "crop"
+    prob = api.Problem((ny, nx), (c["my"], c["mx"]), c["dx"], c["z"], c["lams"], nidx,
+                       weights=c["weights"], out_mode=mode, bandlimit=c["bandlimit"], upsample=up)
+    hd = torch.from_numpy(hc).cuda()
+    ad = None if amp is None else torch.from_numpy(amp).cuda()
+    args = dict(weights=c["weights"], amp=amp, out_mode=mode, bandlimit=c["bandlimit"])
+    want = oracle.psf(hf, c["dx"], c["z"], (c["my"], c["mx"]), c["lams"], nidx, **args)
+    if mode == "crop":
+        got, saved = api.psf(hd, prob, amp=ad, save_fields=True)
+    else:
+        got = api.psf(hd, prob, amp=ad)
+    got = got.cpu().numpy()
+    assert got.shape == want.shape
+    assert np.linalg.norm(got - want) <= 2e-5 * np.linalg.norm(want)
+    if mode == "crop":
+        g = rng.standard_normal((ny, nx)).astype(np.float32)
+        gh = api.psf_backward(hd, prob, saved, torch.from_numpy(g).cuda(), amp=ad).cpu().numpy()
+        wg = oracle.psf_backward(hf, c["dx"], c["z"], (c["my"], c["mx"]), c["lams"], nidx, g,
+                                 weights=c["weights"], amp=amp, bandlimit=c["bandlimit"])
+        if up > 1:
+            wg = ups.upsample_adjoint(wg, up, "nearest")
+        assert gh.shape == wg.shape
+        assert np.linalg.norm(gh - wg) <= 1e-4 * np.linalg.norm(wg)

@@ -178,6 +178,13 @@ dop_status dop_propagate(dop_context *ctx, const dop_problem *prob, int k,
 dop_status dop_psf(dop_context *ctx, const dop_problem *prob, const float *h,
                    const float *amp, float *psf, void *saved_u, void *ws,
                    size_t ws_bytes, void *stream);
+/* Wavelength groups: when saved_u is NULL and ws_bytes holds g >= 2 whole
+ * workspaces of dop_workspace_size(DOP_OP_PSF) bytes, dop_psf runs up to
+ * min(g, 4) wavelengths per group (consecutive k): the first pass forms the
+ * group's fields from one read of h, and the last pass adds their
+ * intensities to the PSF in one read-modify-write.  The result is bitwise
+ * the same as one wavelength at a time.  Grids whose x digit has the factor
+ * 67 run one wavelength at a time. */
 
 /*
  * Gradient of a real loss L with respect to h, given grad_psf = dL/dPSF

@@ -208,9 +208,27 @@ def propagate(u_in, prob, k=0, ctx=None, out=None):
     return out
 
 
-def psf(h, prob, amp=None, save_fields=False, ctx=None, out=None):
+def _psf_workspace(ctx, prob, stream, save_fields, group):
+    """Workspace for dop_psf: one field, or room for a group of up to `group`
+    wavelengths (the library then reads h and read-modify-writes the PSF once
+    per group) when the fields are not saved and the memory is free."""
+    field = workspace_size(prob, L.DOP_OP_PSF)
+    g = 1 if save_fields else max(1, min(int(group), prob.k))
+    while g > 1:
+        try:
+            return ctx.workspace(g * field, stream), g * field
+        except torch.cuda.OutOfMemoryError:
+            ctx.release_workspaces()
+            torch.cuda.empty_cache()
+            g //= 2
+    return ctx.workspace(field, stream), field
+
+
+def psf(h, prob, amp=None, save_fields=False, ctx=None, out=None, group=4):
     """Eq. (1)-(4): wavelength-summed PSF of height map h (n x n float32).
-    With save_fields=True also returns the K x n x n complex64 fields."""
+    With save_fields=True also returns the K x n x n complex64 fields.
+    `group` caps the wavelengths processed together (1 = one at a time;
+    the result is bitwise the same)."""
     ctx = ctx or default_context(h.device.index)
     dev = ctx.device
     _need(h, "h", torch.float32, prob.h_shape, dev)
@@ -223,10 +241,9 @@ def psf(h, prob, amp=None, save_fields=False, ctx=None, out=None):
     if save_fields:
         saved = torch.empty((prob.k,) + prob.doe_shape, dtype=torch.complex64, device=h.device)
     stream = _stream_handle(dev)
-    nbytes = workspace_size(prob, L.DOP_OP_PSF)
-    ws = ctx.workspace(nbytes, stream)
+    ws, nbytes = _psf_workspace(ctx, prob, stream, save_fields, group)
     check(lib().dop_psf(ctx.handle, prob.ptr(), _ptr(h), _ptr(amp), _ptr(out), _ptr(saved),
-                        _ptr(ws), ws.numel(), ctypes.c_void_p(stream)), "dop_psf")
+                        _ptr(ws), nbytes, ctypes.c_void_p(stream)), "dop_psf")
     return (out, saved) if save_fields else out
 
 

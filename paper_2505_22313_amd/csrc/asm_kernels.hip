@@ -961,6 +961,20 @@ DEV float2 transfer(double a2y, double a2x, const KParams &p) {
   return s < 1.0 ? w : make_float2(0.f, 0.f);
 }
 
+// Entry q of a per-group constant, selected with constant indices: indexing
+// a kernel-argument array with a run-time value would copy the whole
+// parameter block to scratch memory.
+template <class T>
+DEV T group_value(const T (&a)[kMaxGroup], int q) {
+  static_assert(kMaxGroup == 4, "one select per entry");
+  return q == 0 ? a[0] : q == 1 ? a[1] : q == 2 ? a[2] : a[3];
+}
+
+// One wavelength's term of the PSF (Eq. 4) added to an accumulator: acc +
+// w_k |U|^2 with U = w / (My Mx) folded into wk.  Shared by the per-wavelength
+// and the grouped output stages, so that both round alike.
+DEV float psf_add(float acc, float wk, float2 w) { return acc + wk * (w.x * w.x + w.y * w.y); }
+
 // Element at a 32-bit byte offset from a block-uniform base: the offset is
 // formed in 32-bit arithmetic so the access can take a scalar base plus one
 // 32-bit vector offset instead of a 64-bit address per lane.
@@ -1021,47 +1035,56 @@ DOP_KERNEL(Plan<PID>::TA) void k_pass_a_fwd(KParams p) {
   };
   constexpr int CH = RUNS < 4 ? RUNS : 4;
   const ChunkSeq<CH> seq(ntiles);
+  const int ngroup = INM == IN_PHASE ? p.group : 1;
   if (seq.tile(0) >= 0) fetch(seq.tile(0), threadIdx.x);
   for (int k = 0;; ++k) {
     const int tile = seq.tile(k);
     if (tile == -1) break;
     if (tile < 0) continue;
-    const int tid = loop_tid();
     const int y = tile / RUNS;
     const int xb0 = (tile % RUNS) * RA;
-    __syncthreads();
-    // the DOE field (Eq. 1-2) or the caller's field, from the prefetched values
-    float2 v[FS::PER][FS::R];
+    // a group of wavelengths shares the tile's heights: each one re-reads
+    // them (from L2) while the previous one is transformed, and writes its
+    // own field
+    for (int q = 0; q < ngroup; ++q) {
+      const int tid = loop_tid();
+      __syncthreads();
+      const double turns = ngroup > 1 ? group_value(p.phase_turns_g, q) : p.phase_turns;
+      // the DOE field (Eq. 1-2) or the caller's field, from the prefetched values
+      float2 v[FS::PER][FS::R];
 #pragma unroll
-    for (int i = 0; i < FS::PER; ++i) {
-      const int it = tid + i * T;
-      if (FS::EXACT || it < FS::ITEMS) {
-        int j, b;
-        decode_item<G, FS::R>(it, j, b);
+      for (int i = 0; i < FS::PER; ++i) {
+        const int it = tid + i * T;
+        if (FS::EXACT || it < FS::ITEMS) {
+          int j, b;
+          decode_item<G, FS::R>(it, j, b);
 #pragma unroll
-        for (int t = 0; t < FS::R; ++t) {
-          const float2 r = pre[i][t];
-          if constexpr (INM == IN_PHASE) {
-            v[i][t] = cscale(doe_phase(r.x, p.phase_turns), r.y);  // r.y = 0 past column n
-          } else if constexpr (INM == IN_FIELD) {
-            v[i][t] = r;
-          } else {
-            const int x = BX * (j + t * FS::LR) + xb0 + b;
-            v[i][t] = x < n ? cscale(r, p.two_wk * p.gpsf[(size_t)y * n + x]) : r;
+          for (int t = 0; t < FS::R; ++t) {
+            const float2 r = pre[i][t];
+            if constexpr (INM == IN_PHASE) {
+              v[i][t] = cscale(doe_phase(r.x, turns), r.y);  // r.y = 0 past column n
+            } else if constexpr (INM == IN_FIELD) {
+              v[i][t] = r;
+            } else {
+              const int x = BX * (j + t * FS::LR) + xb0 + b;
+              v[i][t] = x < n ? cscale(r, p.two_wk * p.gpsf[(size_t)y * n + x]) : r;
+            }
           }
         }
       }
+      if (q + 1 < ngroup) {
+        fetch(tile, tid);
+      } else {
+        const int nt = seq.tile(k + 1) >= 0 ? seq.tile(k + 1) : seq.tile(k + 2);
+        if (nt >= 0) fetch(nt, tid);
+      }
+      float2 *out = p.ws + (size_t)q * p.field_elems + (size_t)y * P::PITCH;
+      auto st = [&](int kxa, int b, float2 w) {
+        const int xb = xb0 + b;
+        out[BX * kxa + xb] = cmul(w, tw_q<PID>(tw, xb * kxa));
+      };
+      dft_tile<G, false, false, SRC_REG, SNK_FN, P::THI>(lds, tw.hi, NoLoad{}, st, v, tid);
     }
-    {
-      const int nt = seq.tile(k + 1) >= 0 ? seq.tile(k + 1) : seq.tile(k + 2);
-      if (nt >= 0) fetch(nt, tid);
-    }
-    float2 *out = p.ws + (size_t)y * P::PITCH;
-    auto st = [&](int kxa, int b, float2 w) {
-      const int xb = xb0 + b;
-      out[BX * kxa + xb] = cmul(w, tw_q<PID>(tw, xb * kxa));
-    };
-    dft_tile<G, false, false, SRC_REG, SNK_FN, P::THI>(lds, tw.hi, NoLoad{}, st, v, tid);
   }
 }
 
@@ -1362,10 +1385,15 @@ DOP_KERNEL(Plan<PID>::TA) void k_pass_a_inv(KParams p) {
   const int ntiles = p.nrows_out * RUNS;
   const int n = p.n;
   const bool accumulate = (OUTM == OUT_PSF || OUTM == OUT_GRADH) && !p.first;
+  // a group of wavelengths (PSF output, no saved fields) adds all its
+  // intensities to one read-modify-write of the PSF; field q of the group
+  // sits q * field_elems after the first
+  const int ngroup = (OUTM == OUT_PSF && !VIA_FN) ? p.group : 1;
   // spectrum values of one tile's first inverse stage, loaded one tile ahead
   float2 pre[FS::PER][FS::R];
-  auto fetch = [&](int tile, int tid) {
-    const float2 *row = p.ws + (size_t)(tile / RUNS) * P::PITCH + (tile % RUNS) * RA;
+  auto fetch = [&](int tile, int tid, int q) {
+    const float2 *row = p.ws + (size_t)q * p.field_elems + (size_t)(tile / RUNS) * P::PITCH +
+                        (tile % RUNS) * RA;
 #pragma unroll
     for (int i = 0; i < FS::PER; ++i) {
       const int it = tid + i * T;
@@ -1388,10 +1416,10 @@ DOP_KERNEL(Plan<PID>::TA) void k_pass_a_inv(KParams p) {
     return x < n ? (long long)y * n + x : -1;
   };
   // output stage of one element: w is My Mx U (the inverse DFT's 1/(My Mx)
-  // is applied here), accv the accumulator value it adds to
-  auto finish = [&](int y, int x, long long idx, float2 w, float accv) {
+  // is applied here), accv the accumulator value it adds to, wk the PSF weight
+  auto finish = [&](int y, int x, long long idx, float2 w, float accv, float wk) {
     if constexpr (OUTM == OUT_PSF) {
-      p.psf[idx] = accv + p.wk_m4 * (w.x * w.x + w.y * w.y);
+      p.psf[idx] = psf_add(accv, wk, w);
       if (p.saved_out) p.saved_out[idx] = cscale(w, p.inv_m2);
     } else if constexpr (OUTM == OUT_FIELD) {
       p.u_out[idx] = cscale(w, p.inv_m2);
@@ -1406,77 +1434,89 @@ DOP_KERNEL(Plan<PID>::TA) void k_pass_a_inv(KParams p) {
   };
   constexpr int CH = RUNS < 4 ? RUNS : 4;
   const ChunkSeq<CH> seq(ntiles);
-  if (seq.tile(0) >= 0) fetch(seq.tile(0), threadIdx.x);
+  if (seq.tile(0) >= 0) fetch(seq.tile(0), threadIdx.x, 0);
   for (int k = 0;; ++k) {
     const int tile = seq.tile(k);
     if (tile == -1) break;
     if (tile < 0) continue;
-    const int tid = loop_tid();
     const int y = tile / RUNS;
     const int xb0 = (tile % RUNS) * RA;
-    __syncthreads();
-    float2 v[FS::PER][FS::R];
-#pragma unroll
-    for (int i = 0; i < FS::PER; ++i) {
-      const int it = tid + i * T;
-      if (FS::EXACT || it < FS::ITEMS) {
-        int j, b;
-        decode_item<G, FS::R>(it, j, b);
-#pragma unroll
-        for (int t = 0; t < FS::R; ++t)
-          v[i][t] = cmulc(pre[i][t], tw_q<PID>(tw, (xb0 + b) * (j + t * FS::LR)));
-      }
-    }
-    // After the first stage: read the accumulator values this tile will add
-    // to, then start the next tile's loads.  Loads complete in issue order, so
-    // the accumulator reads go first: waiting for them at the end of this
-    // tile must not also wait for the prefetch.
     float acc[APER][AR];
-    auto hook = [&]() {
-      if constexpr (!VIA_FN) {
+    for (int q = 0; q < ngroup; ++q) {
+      const int tid = loop_tid();
+      __syncthreads();
+      const float wk = ngroup > 1 ? group_value(p.wk_m4_g, q) : p.wk_m4;
+      float2 v[FS::PER][FS::R];
 #pragma unroll
-        for (int i = 0; i < LS::PER; ++i) {
-          const int it = tid + i * T;
-          int j = 0, b = 0;
-          if (SSL::EXACT || it < SSL::ITEMS) decode_item<G, LS::R>(it, j, b);
+      for (int i = 0; i < FS::PER; ++i) {
+        const int it = tid + i * T;
+        if (FS::EXACT || it < FS::ITEMS) {
+          int j, b;
+          decode_item<G, FS::R>(it, j, b);
 #pragma unroll
-          for (int t = 0; t < LS::R; ++t) {
-            acc[i][t] = 0.f;
-            if (accumulate && (SSL::EXACT || it < SSL::ITEMS)) {
-              const long long idx = out_index(y, xb0, j + t * LRL, b);
-              if (idx >= 0) acc[i][t] = (OUTM == OUT_PSF) ? p.psf[idx] : p.grad_h[idx];
+          for (int t = 0; t < FS::R; ++t)
+            v[i][t] = cmulc(pre[i][t], tw_q<PID>(tw, (xb0 + b) * (j + t * FS::LR)));
+        }
+      }
+      // After the first stage: read the accumulator values this tile will
+      // add to (once per group), then start the next loads (the group's next
+      // field of this tile, else the next tile).  Loads complete in issue
+      // order, so the accumulator reads go first: waiting for them at the end
+      // of this tile must not also wait for the prefetch.
+      auto hook = [&]() {
+        if constexpr (!VIA_FN) {
+          if (q == 0) {
+#pragma unroll
+            for (int i = 0; i < LS::PER; ++i) {
+              const int it = tid + i * T;
+              int j = 0, b = 0;
+              if (SSL::EXACT || it < SSL::ITEMS) decode_item<G, LS::R>(it, j, b);
+#pragma unroll
+              for (int t = 0; t < LS::R; ++t) {
+                acc[i][t] = 0.f;
+                if (accumulate && (SSL::EXACT || it < SSL::ITEMS)) {
+                  const long long idx = out_index(y, xb0, j + t * LRL, b);
+                  if (idx >= 0) acc[i][t] = (OUTM == OUT_PSF) ? p.psf[idx] : p.grad_h[idx];
+                }
+              }
             }
           }
         }
-      }
-      const int nt = seq.tile(k + 1) >= 0 ? seq.tile(k + 1) : seq.tile(k + 2);
-      if (nt >= 0) fetch(nt, tid);
-    };
-    if constexpr (VIA_FN) {
-      float2 dummy[1][1];
-      auto st = [&](int xa, int b, float2 w) {
-        const long long idx = out_index(y, xb0, xa, b);
-        if (idx < 0) return;
-        const float accv = !accumulate ? 0.f : (OUTM == OUT_PSF) ? p.psf[idx] : p.grad_h[idx];
-        finish(y, BX * xa + xb0 + b, idx, w, accv);
+        if (q + 1 < ngroup) {
+          fetch(tile, tid, q + 1);
+        } else {
+          const int nt = seq.tile(k + 1) >= 0 ? seq.tile(k + 1) : seq.tile(k + 2);
+          if (nt >= 0) fetch(nt, tid, 0);
+        }
       };
-      dft_tile_hooked<G, true, false, SRC_REG, SNK_FN, P::THI>(lds, tw.hi, NoLoad{}, st, hook, v,
-                                                              dummy, tid);
-    } else {
-      float2 u[LS::PER][LS::R];
-      dft_tile_hooked<G, true, false, SRC_REG, SNK_REG, P::THI>(lds, tw.hi, NoLoad{}, NoStore{},
-                                                               hook, v, u, tid);
+      if constexpr (VIA_FN) {
+        float2 dummy[1][1];
+        auto st = [&](int xa, int b, float2 w) {
+          const long long idx = out_index(y, xb0, xa, b);
+          if (idx < 0) return;
+          const float accv = !accumulate ? 0.f : (OUTM == OUT_PSF) ? p.psf[idx] : p.grad_h[idx];
+          finish(y, BX * xa + xb0 + b, idx, w, accv, wk);
+        };
+        dft_tile_hooked<G, true, false, SRC_REG, SNK_FN, P::THI>(lds, tw.hi, NoLoad{}, st, hook, v,
+                                                                dummy, tid);
+      } else {
+        float2 u[LS::PER][LS::R];
+        dft_tile_hooked<G, true, false, SRC_REG, SNK_REG, P::THI>(lds, tw.hi, NoLoad{}, NoStore{},
+                                                                 hook, v, u, tid);
+        const bool last = q + 1 == ngroup;
 #pragma unroll
-      for (int i = 0; i < LS::PER; ++i) {
-        const int it = tid + i * T;
-        if (SSL::EXACT || it < SSL::ITEMS) {
-          int j, b;
-          decode_item<G, LS::R>(it, j, b);
+        for (int i = 0; i < LS::PER; ++i) {
+          const int it = tid + i * T;
+          if (SSL::EXACT || it < SSL::ITEMS) {
+            int j, b;
+            decode_item<G, LS::R>(it, j, b);
 #pragma unroll
-          for (int t = 0; t < LS::R; ++t) {
-            const long long idx = out_index(y, xb0, j + t * LRL, b);
-            if (idx < 0) continue;
-            finish(y, BX * (j + t * LRL) + xb0 + b, idx, u[i][t], acc[i][t]);
+            for (int t = 0; t < LS::R; ++t) {
+              const long long idx = out_index(y, xb0, j + t * LRL, b);
+              if (idx < 0) continue;
+              if (last) finish(y, BX * (j + t * LRL) + xb0 + b, idx, u[i][t], acc[i][t], wk);
+              else acc[i][t] = psf_add(acc[i][t], wk, u[i][t]);
+            }
           }
         }
       }
@@ -1492,7 +1532,8 @@ static inline void mark(hipEvent_t *ev, int i, hipStream_t s) {
 }
 
 template <int PID>
-static hipError_t launch_impl(const KParams &p, hipStream_t s, hipEvent_t *ev) {
+static hipError_t launch_range(const KParams &p, int first, int last, hipStream_t s,
+                               hipEvent_t *ev) {
   using P = Plan<PID>;
   auto grid = [](long long tiles) {
     return (unsigned)(tiles < kMaxBlocks ? tiles : kMaxBlocks);
@@ -1501,62 +1542,71 @@ static hipError_t launch_impl(const KParams &p, hipStream_t s, hipEvent_t *ev) {
   const unsigned gb = grid((long long)P::AX * P::BY);
   const unsigned gc = grid((long long)P::AY * (P::MX / P::RC));
   const unsigned gai = grid((long long)p.nrows_out * (P::BX / P::RA));
-  mark(ev, 0, s);
-  if (p.in_mode == IN_PHASE)
-    hipLaunchKernelGGL((k_pass_a_fwd<PID, IN_PHASE>), dim3(ga), dim3(P::TA), 0, s, p);
-  else if (p.in_mode == IN_FIELD)
-    hipLaunchKernelGGL((k_pass_a_fwd<PID, IN_FIELD>), dim3(ga), dim3(P::TA), 0, s, p);
-  else
-    hipLaunchKernelGGL((k_pass_a_fwd<PID, IN_GRAD>), dim3(ga), dim3(P::TA), 0, s, p);
-  mark(ev, 1, s);
-  hipLaunchKernelGGL(k_pass_b_fwd<PID>, dim3(gb), dim3(P::TB), 0, s, p);
-  mark(ev, 2, s);
-  hipLaunchKernelGGL(k_pass_c<PID>, dim3(gc), dim3(P::TC), 0, s, p);
-  mark(ev, 3, s);
-  hipLaunchKernelGGL(k_pass_b_inv<PID>, dim3(gb), dim3(P::TB), 0, s, p);
-  mark(ev, 4, s);
-  if (p.out_mode == OUT_PSF)
-    hipLaunchKernelGGL((k_pass_a_inv<PID, OUT_PSF>), dim3(gai), dim3(P::TA), 0, s, p);
-  else if (p.out_mode == OUT_FIELD)
-    hipLaunchKernelGGL((k_pass_a_inv<PID, OUT_FIELD>), dim3(gai), dim3(P::TA), 0, s, p);
-  else
-    hipLaunchKernelGGL((k_pass_a_inv<PID, OUT_GRADH>), dim3(gai), dim3(P::TA), 0, s, p);
-  mark(ev, 5, s);
+  for (int pass = first; pass <= last; ++pass) {
+    mark(ev, pass - first, s);
+    switch (pass) {
+      case 0:
+        if (p.in_mode == IN_PHASE)
+          hipLaunchKernelGGL((k_pass_a_fwd<PID, IN_PHASE>), dim3(ga), dim3(P::TA), 0, s, p);
+        else if (p.in_mode == IN_FIELD)
+          hipLaunchKernelGGL((k_pass_a_fwd<PID, IN_FIELD>), dim3(ga), dim3(P::TA), 0, s, p);
+        else
+          hipLaunchKernelGGL((k_pass_a_fwd<PID, IN_GRAD>), dim3(ga), dim3(P::TA), 0, s, p);
+        break;
+      case 1: hipLaunchKernelGGL(k_pass_b_fwd<PID>, dim3(gb), dim3(P::TB), 0, s, p); break;
+      case 2: hipLaunchKernelGGL(k_pass_c<PID>, dim3(gc), dim3(P::TC), 0, s, p); break;
+      case 3: hipLaunchKernelGGL(k_pass_b_inv<PID>, dim3(gb), dim3(P::TB), 0, s, p); break;
+      default:
+        if (p.out_mode == OUT_PSF)
+          hipLaunchKernelGGL((k_pass_a_inv<PID, OUT_PSF>), dim3(gai), dim3(P::TA), 0, s, p);
+        else if (p.out_mode == OUT_FIELD)
+          hipLaunchKernelGGL((k_pass_a_inv<PID, OUT_FIELD>), dim3(gai), dim3(P::TA), 0, s, p);
+        else
+          hipLaunchKernelGGL((k_pass_a_inv<PID, OUT_GRADH>), dim3(gai), dim3(P::TA), 0, s, p);
+        break;
+    }
+  }
+  mark(ev, last - first + 1, s);
   return hipGetLastError();
 }
 
-hipError_t launch_wavelength(const KParams &p, hipStream_t s, hipEvent_t *ev) {
+hipError_t launch_passes(const KParams &p, int first, int last, hipStream_t s, hipEvent_t *ev) {
+  if (first < 0 || last >= kNumPasses || first > last) return hipErrorInvalidValue;
   switch (p.plan) {
-    case 4: return launch_impl<4>(p, s, ev);
-    case 5: return launch_impl<5>(p, s, ev);
-    case 6: return launch_impl<6>(p, s, ev);
-    case 7: return launch_impl<7>(p, s, ev);
-    case 8: return launch_impl<8>(p, s, ev);
-    case 9: return launch_impl<9>(p, s, ev);
-    case 10: return launch_impl<10>(p, s, ev);
-    case 11: return launch_impl<11>(p, s, ev);
-    case 12: return launch_impl<12>(p, s, ev);
-    case 13: return launch_impl<13>(p, s, ev);
-    case 14: return launch_impl<14>(p, s, ev);
-    case 15: return launch_impl<15>(p, s, ev);
-    case 16: return launch_impl<16>(p, s, ev);
-    case 17: return launch_impl<17>(p, s, ev);
-    case kTabBase + 0: return launch_impl<kTabBase + 0>(p, s, ev);
-    case kTabBase + 1: return launch_impl<kTabBase + 1>(p, s, ev);
-    case kTabBase + 2: return launch_impl<kTabBase + 2>(p, s, ev);
-    case kTabBase + 3: return launch_impl<kTabBase + 3>(p, s, ev);
-    case kTabBase + 4: return launch_impl<kTabBase + 4>(p, s, ev);
-    case kTabBase + 5: return launch_impl<kTabBase + 5>(p, s, ev);
-    case kTabBase + 6: return launch_impl<kTabBase + 6>(p, s, ev);
-    case kTabBase + 7: return launch_impl<kTabBase + 7>(p, s, ev);
-    case kTabBase + 8: return launch_impl<kTabBase + 8>(p, s, ev);
-    case kTabBase + 9: return launch_impl<kTabBase + 9>(p, s, ev);
-    case kTabBase + 10: return launch_impl<kTabBase + 10>(p, s, ev);
-    case kTabBase + 11: return launch_impl<kTabBase + 11>(p, s, ev);
-    case kTabBase + 12: return launch_impl<kTabBase + 12>(p, s, ev);
-    case kTabBase + 13: return launch_impl<kTabBase + 13>(p, s, ev);
+    case 4: return launch_range<4>(p, first, last, s, ev);
+    case 5: return launch_range<5>(p, first, last, s, ev);
+    case 6: return launch_range<6>(p, first, last, s, ev);
+    case 7: return launch_range<7>(p, first, last, s, ev);
+    case 8: return launch_range<8>(p, first, last, s, ev);
+    case 9: return launch_range<9>(p, first, last, s, ev);
+    case 10: return launch_range<10>(p, first, last, s, ev);
+    case 11: return launch_range<11>(p, first, last, s, ev);
+    case 12: return launch_range<12>(p, first, last, s, ev);
+    case 13: return launch_range<13>(p, first, last, s, ev);
+    case 14: return launch_range<14>(p, first, last, s, ev);
+    case 15: return launch_range<15>(p, first, last, s, ev);
+    case 16: return launch_range<16>(p, first, last, s, ev);
+    case 17: return launch_range<17>(p, first, last, s, ev);
+    case kTabBase + 0: return launch_range<kTabBase + 0>(p, first, last, s, ev);
+    case kTabBase + 1: return launch_range<kTabBase + 1>(p, first, last, s, ev);
+    case kTabBase + 2: return launch_range<kTabBase + 2>(p, first, last, s, ev);
+    case kTabBase + 3: return launch_range<kTabBase + 3>(p, first, last, s, ev);
+    case kTabBase + 4: return launch_range<kTabBase + 4>(p, first, last, s, ev);
+    case kTabBase + 5: return launch_range<kTabBase + 5>(p, first, last, s, ev);
+    case kTabBase + 6: return launch_range<kTabBase + 6>(p, first, last, s, ev);
+    case kTabBase + 7: return launch_range<kTabBase + 7>(p, first, last, s, ev);
+    case kTabBase + 8: return launch_range<kTabBase + 8>(p, first, last, s, ev);
+    case kTabBase + 9: return launch_range<kTabBase + 9>(p, first, last, s, ev);
+    case kTabBase + 10: return launch_range<kTabBase + 10>(p, first, last, s, ev);
+    case kTabBase + 11: return launch_range<kTabBase + 11>(p, first, last, s, ev);
+    case kTabBase + 12: return launch_range<kTabBase + 12>(p, first, last, s, ev);
+    case kTabBase + 13: return launch_range<kTabBase + 13>(p, first, last, s, ev);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_wavelength(const KParams &p, hipStream_t s, hipEvent_t *ev) {
+  return launch_passes(p, 0, kNumPasses - 1, s, ev);
 }
 static_assert(kNumTab == 14, "one launch case per grid of table_plan");
 
@@ -1583,6 +1633,14 @@ static void fill_plan(PlanInfo *o) {
   using P = Plan<PID>;
   o->ax = P::AX; o->bx = P::BX; o->ay = P::AY; o->by = P::BY; o->ra = P::RA; o->rc = P::RC;
   o->threads_a = P::TA; o->threads_b = P::TB; o->threads_c = P::TC;
+}
+
+// A group of wavelengths needs pass A' to hold the accumulator in registers,
+// which a radix-67 last stage (writing through a store functor) does not.
+int plan_max_group(int plan) {
+  PlanInfo o;
+  if (!plan_info(plan, &o)) return 0;
+  return o.ax % kP == 0 ? 1 : kMaxGroup;
 }
 
 bool plan_info(int plan, PlanInfo *o) {

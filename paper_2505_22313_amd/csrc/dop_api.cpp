@@ -21,7 +21,12 @@ struct dop_context {
   std::mutex prof_mu;
   bool prof_on = false;
   std::vector<hipEvent_t> prof_pool;            // idle events
-  std::vector<std::vector<hipEvent_t>> pending;  // 6 events per wavelength launch
+  // marks around launched passes first, first + 1, ... (one more event than passes)
+  struct Pending {
+    std::vector<hipEvent_t> ev;
+    int first;
+  };
+  std::vector<Pending> pending;
   double prof_ms[dop::kNumPasses] = {0, 0, 0, 0, 0};
   uint64_t prof_n[dop::kNumPasses] = {0, 0, 0, 0, 0};
 };
@@ -162,15 +167,20 @@ void fill_common(KParams &kp, const dop_context *ctx, const dop_problem *prob, i
   kp.two_wk = 2.0f * w;
   kp.ck_m2 = (float)(2.0 * M_PI * (prob->n_index[k] - 1.0) / lam / m2);
   kp.inv_m2 = (float)(1.0 / m2);
+  kp.group = 1;
+  kp.field_elems = workspace_bytes(prob) / sizeof(float2);
 }
 
-dop_status launch(const dop_context *cctx, const KParams &kp, hipStream_t stream) {
+// Enqueue passes first..last of kp (0 = A ... 4 = A'), bracketed by timing
+// events while profiling is on.
+dop_status launch_range(const dop_context *cctx, const KParams &kp, int first, int last,
+                        hipStream_t stream) {
   dop_context *ctx = const_cast<dop_context *>(cctx);
   std::vector<hipEvent_t> ev;
   {
     std::lock_guard<std::mutex> lk(ctx->prof_mu);
     if (ctx->prof_on) {
-      while ((int)ev.size() < kNumPasses + 1) {
+      while ((int)ev.size() < last - first + 2) {
         hipEvent_t e = nullptr;
         if (!ctx->prof_pool.empty()) {
           e = ctx->prof_pool.back();
@@ -182,13 +192,17 @@ dop_status launch(const dop_context *cctx, const KParams &kp, hipStream_t stream
       }
     }
   }
-  const hipError_t e = launch_wavelength(kp, stream, ev.empty() ? nullptr : ev.data());
+  const hipError_t e = launch_passes(kp, first, last, stream, ev.empty() ? nullptr : ev.data());
   if (!ev.empty()) {
     std::lock_guard<std::mutex> lk(ctx->prof_mu);
-    ctx->pending.push_back(std::move(ev));
+    ctx->pending.push_back({std::move(ev), first});
   }
   if (e != hipSuccess) return fail(DOP_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
   return DOP_OK;
+}
+
+dop_status launch(const dop_context *ctx, const KParams &kp, hipStream_t stream) {
+  return launch_range(ctx, kp, 0, kNumPasses - 1, stream);
 }
 
 dop_status check_ctx_device(const dop_context *ctx) {
@@ -200,23 +214,67 @@ dop_status check_ctx_device(const dop_context *ctx) {
   return DOP_OK;
 }
 
+int psf_group(const dop_problem *prob, const void *saved_u, size_t ws_bytes) {
+  if (saved_u) return 1;
+  const size_t field = workspace_bytes(prob);
+  const int g = plan_max_group(plan_id(grid_cols(prob), grid_rows(prob)));
+  const size_t fit = ws_bytes / field;
+  int r = prob->n_lambda < g ? prob->n_lambda : g;
+  if (fit < (size_t)r) r = (int)fit;
+  return r < 1 ? 1 : r;
+}
+
 dop_status enqueue_psf(const dop_context *ctx, const dop_problem *prob, const float *h,
-                       const float *amp, float *psf, void *saved_u, void *ws, hipStream_t stream) {
+                       const float *amp, float *psf, void *saved_u, void *ws, size_t ws_bytes,
+                       hipStream_t stream) {
   const size_t nn = (size_t)doe_rows(prob) * prob->n;
-  for (int k = 0; k < prob->n_lambda; ++k) {
-    KParams kp;
-    fill_common(kp, ctx, prob, k, ws);
+  const int g = psf_group(prob, saved_u, ws_bytes);
+  auto setup = [&](KParams &kp, int k, void *field) {
+    fill_common(kp, ctx, prob, k, field);
     kp.in_mode = IN_PHASE;
     kp.out_mode = OUT_PSF;
     kp.full = prob->out_mode == DOP_OUT_FULL;
     kp.nrows_out = kp.full ? grid_rows(prob) : doe_rows(prob);
-    kp.first = (k == 0);
     kp.h = h;
     kp.amp = amp;
     kp.psf = psf;
-    kp.saved_out = saved_u ? static_cast<float2 *>(saved_u) + (size_t)k * nn : nullptr;
-    const dop_status s = launch(ctx, kp, stream);
-    if (s != DOP_OK) return s;
+  };
+  for (int k0 = 0; k0 < prob->n_lambda;) {
+    const int gk = prob->n_lambda - k0 < g ? prob->n_lambda - k0 : g;
+    if (gk == 1) {
+      KParams kp;
+      setup(kp, k0, ws);
+      kp.first = (k0 == 0);
+      kp.saved_out = saved_u ? static_cast<float2 *>(saved_u) + (size_t)k0 * nn : nullptr;
+      const dop_status s = launch(ctx, kp, stream);
+      if (s != DOP_OK) return s;
+    } else {
+      // a group: pass A forms the gk fields from one read of the heights,
+      // passes B, C, B' run per field, pass A' adds the gk intensities to
+      // the PSF in one read-modify-write (the same sums in the same order
+      // as one wavelength at a time)
+      KParams g0;
+      setup(g0, k0, ws);
+      g0.first = (k0 == 0);
+      g0.group = gk;
+      for (int q = 0; q < gk; ++q) {
+        KParams kq;
+        setup(kq, k0 + q, ws);
+        g0.phase_turns_g[q] = kq.phase_turns;
+        g0.wk_m4_g[q] = kq.wk_m4;
+      }
+      dop_status s = launch_range(ctx, g0, 0, 0, stream);
+      if (s != DOP_OK) return s;
+      for (int q = 0; q < gk; ++q) {
+        KParams kq;
+        setup(kq, k0 + q, static_cast<float2 *>(ws) + (size_t)q * g0.field_elems);
+        s = launch_range(ctx, kq, 1, 3, stream);
+        if (s != DOP_OK) return s;
+      }
+      s = launch_range(ctx, g0, kNumPasses - 1, kNumPasses - 1, stream);
+      if (s != DOP_OK) return s;
+    }
+    k0 += gk;
   }
   return DOP_OK;
 }
@@ -284,8 +342,8 @@ dop_status dop_context_destroy(dop_context *ctx) {
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(ctx->device);
-  for (auto &v : ctx->pending)
-    for (hipEvent_t e : v) {
+  for (auto &pl : ctx->pending)
+    for (hipEvent_t e : pl.ev) {
       (void)hipEventSynchronize(e);
       (void)hipEventDestroy(e);
     }
@@ -301,15 +359,16 @@ static const char *kPassNames[kNumPasses] = {"pass_a_fwd", "pass_b_fwd", "pass_c
 
 // Wait for the pending events and fold their intervals into the totals.
 static dop_status collect(dop_context *ctx) {
-  for (auto &v : ctx->pending) {
+  for (auto &pl : ctx->pending) {
+    const std::vector<hipEvent_t> &v = pl.ev;
     if (hipEventSynchronize(v.back()) != hipSuccess)
       return fail(DOP_ERR_DEVICE, "hipEventSynchronize failed");
-    for (int i = 0; i < kNumPasses; ++i) {
+    for (size_t i = 0; i + 1 < v.size(); ++i) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, v[i], v[i + 1]) != hipSuccess)
         return fail(DOP_ERR_DEVICE, "hipEventElapsedTime failed");
-      ctx->prof_ms[i] += ms;
-      ctx->prof_n[i] += 1;
+      ctx->prof_ms[pl.first + i] += ms;
+      ctx->prof_n[pl.first + i] += 1;
     }
     for (hipEvent_t e : v) ctx->prof_pool.push_back(e);
   }
@@ -417,7 +476,8 @@ dop_status dop_psf(dop_context *ctx, const dop_problem *prob, const float *h, co
     return fail(DOP_ERR_INVALID_ARG, "saved_u must be 8-byte aligned");
   if ((s = check_ws(prob, DOP_OP_PSF, ws, ws_bytes)) != DOP_OK) return s;
   if ((s = check_ctx_device(ctx)) != DOP_OK) return s;
-  return enqueue_psf(ctx, prob, h, amp, psf, saved_u, ws, static_cast<hipStream_t>(stream));
+  return enqueue_psf(ctx, prob, h, amp, psf, saved_u, ws, ws_bytes,
+                     static_cast<hipStream_t>(stream));
 }
 
 dop_status dop_psf_backward(dop_context *ctx, const dop_problem *prob, const float *h,

@@ -25,9 +25,17 @@ dop_status validate_problem(const dop_problem *prob);
 // Workspace bytes of any operation on `prob` (one My x Mx complex64 field).
 size_t workspace_bytes(const dop_problem *prob);
 
-// Enqueue the whole PSF of `prob` (all wavelengths) on `stream`.
+// Enqueue the whole PSF of `prob` (all wavelengths) on `stream`.  A workspace
+// of g >= 2 fields (ws_bytes) lets wavelengths run in groups of up to g (see
+// psf_group).
 dop_status enqueue_psf(const dop_context *ctx, const dop_problem *prob, const float *h,
-                       const float *amp, float *psf, void *saved_u, void *ws, hipStream_t stream);
+                       const float *amp, float *psf, void *saved_u, void *ws, size_t ws_bytes,
+                       hipStream_t stream);
+
+// Wavelengths per group that dop_psf uses for `prob` with a workspace of
+// ws_bytes: as many whole fields as fit, at most the plan's limit and the
+// wavelength count, and 1 when the fields are saved.
+int psf_group(const dop_problem *prob, const void *saved_u, size_t ws_bytes);
 
 int context_device(const dop_context *ctx);
 

@@ -12,6 +12,10 @@ namespace dop {
 constexpr int kTwLog = 17;
 constexpr int kTwN = 1 << kTwLog;
 
+// Wavelengths per group: pass A forms, and pass A' accumulates, up to this
+// many fields (one workspace field each) per launch.
+constexpr int kMaxGroup = 4;
+
 // Row pitch of the M x M workspace, in elements: M + kRowPad.  The pad keeps
 // rows that are a power of two apart from landing on the same HBM channels
 // (column passes read hundreds of rows at one column offset).
@@ -70,6 +74,13 @@ struct KParams {
   float two_wk;          // 2 w_k
   float ck_m2;           // 2 pi (n_k - 1) / lambda_k / (My Mx)
   float inv_m2;          // 1 / (My Mx) (inverse-DFT normalisation of output fields)
+  int group;             // wavelengths in this launch of pass A (IN_PHASE) or A'
+                         // (OUT_PSF, no saved fields): 1, or 2..kMaxGroup with
+                         // their fields field_elems apart and the per-wavelength
+                         // constants below
+  size_t field_elems;    // elements from one field of a group to the next
+  double phase_turns_g[kMaxGroup];
+  float wk_m4_g[kMaxGroup];
 };
 
 constexpr int kNumPasses = 5;
@@ -78,6 +89,15 @@ constexpr int kNumPasses = 5;
 // NULL, ev[0..5] are recorded before the first pass, between passes and
 // after the last one.
 hipError_t launch_wavelength(const KParams &p, hipStream_t stream, hipEvent_t *ev);
+
+// Enqueue passes first..last (0 = A, 1 = B, 2 = C, 3 = B', 4 = A') of `p`;
+// ev (if not NULL) gets last - first + 2 marks around them.
+hipError_t launch_passes(const KParams &p, int first, int last, hipStream_t stream,
+                         hipEvent_t *ev);
+
+// Largest wavelength group the plan supports (1 if pass A' ends in a
+// radix-67 stage), 0 for an unknown plan.
+int plan_max_group(int plan);
 
 // Plan id of the My x Mx grid (mx columns, my rows): log2(M) for a square
 // power of two M in [16, 131072], a larger id for each grid of the plan

@@ -127,8 +127,9 @@ class GpuExecutor : public Executor {
       if (s) (void)hipStreamDestroy(s);
   }
   void thread_init() override { (void)hipSetDevice(context_device(ctx_)); }
-  dop_status start(int slot, Request &r, void *ws, size_t) override {
-    dop_status s = enqueue_psf(ctx_, &r.prob, r.h, r.amp, r.psf, nullptr, ws, streams_[slot]);
+  dop_status start(int slot, Request &r, void *ws, size_t ws_bytes) override {
+    dop_status s =
+        enqueue_psf(ctx_, &r.prob, r.h, r.amp, r.psf, nullptr, ws, ws_bytes, streams_[slot]);
     if (s != DOP_OK) return s;
     if (hipEventRecord(events_[slot], streams_[slot]) != hipSuccess)
       return fail(DOP_ERR_DEVICE, "hipEventRecord failed");

@@ -80,3 +80,27 @@ def test_bench_byte_model():
     assert sum(steady.values()) - sum(first.values()) == pytest.approx(4.0 * (m // 2) ** 2)
     full = bench.pass_bytes(m, m, k_first=False)
     assert sum(full.values()) / m ** 2 == pytest.approx(64.0 + 4.0 + 8.0)
+
+
+def test_bench_group_byte_model():
+    """Wavelength groups: pass A reads h once per group and pass A' touches
+    the PSF once per group; one group per wavelength is the per-wavelength
+    accounting (the first wavelength writes the PSF without reading it)."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    n, m, k = 32768, 65536, 31
+    per = bench.step_pass_bytes(n, m, k, k)
+    steady = bench.pass_bytes(n, m, k_first=False)
+    first = bench.pass_bytes(n, m, k_first=True)
+    for name in per:
+        assert per[name] == pytest.approx(first[name] + (k - 1) * steady[name])
+    grouped = bench.step_pass_bytes(n, m, k, 8)  # 7 groups of 4 and one of 3
+    saved = sum(per.values()) - sum(grouped.values())
+    assert saved == pytest.approx((k - 8) * (4.0 * n * n + 8.0 * n * n))
+    assert sum(grouped.values()) / (k * float(m) * m) == pytest.approx(48.74, abs=0.01)
+    # rectangular: rows x columns
+    r = bench.step_pass_bytes((300, 200), (720, 240), 2, 1)
+    assert r["pass_a_fwd"] == pytest.approx(2 * 8.0 * 300 * 240 + 4.0 * 300 * 200)
+    assert r["pass_c"] == pytest.approx(2 * 2 * 8.0 * 720 * 240)

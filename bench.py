@@ -447,6 +447,8 @@ def main():
     ap.add_argument("--lambdas", type=int, default=0,
                     help="profiling runs only: keep the first K wavelengths")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--group", type=int, default=4,
+                    help="wavelengths per group in the timed PSF calls (1 = one at a time)")
     ap.add_argument("--no-design", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--no-variants", action="store_true",
@@ -493,7 +495,7 @@ def main():
     log("inputs resident on the GPU; warming up")
 
     for i in range(args.warmup):
-        api.psf(hd, prob, out=psf, ctx=ctx)
+        api.psf(hd, prob, out=psf, ctx=ctx, group=args.group)
         torch.cuda.synchronize()
         log(f"warmup step {i + 1}/{args.warmup} done")
 
@@ -503,7 +505,7 @@ def main():
     t0 = time.perf_counter()
     marks[0].record()
     for i in range(args.steps):
-        api.psf(hd, prob, out=psf, ctx=ctx)
+        api.psf(hd, prob, out=psf, ctx=ctx, group=args.group)
         marks[i + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()

@@ -115,6 +115,7 @@ class Context:
         self.handle = h
         self._ws = {}
         self._lock = threading.Lock()
+        self.group_cap = {}  # field bytes -> largest wavelength group that fitted
 
     def workspace(self, nbytes, stream):
         """Cached device workspace of at least nbytes for this stream."""
@@ -127,6 +128,12 @@ class Context:
                 buf = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{self.device}")
                 self._ws[key] = buf
         return buf
+
+    def workspace_bytes(self, stream):
+        """Bytes of the workspace cached for this stream (0 if none)."""
+        with self._lock:
+            buf = self._ws.get(int(stream))
+            return 0 if buf is None else buf.numel()
 
     def profile_enable(self, enable=True):
         """Start (clearing the totals) or stop per-pass HIP-event timing."""
@@ -213,14 +220,20 @@ def _psf_workspace(ctx, prob, stream, save_fields, group):
     wavelengths (the library then reads h and read-modify-writes the PSF once
     per group) when the fields are not saved and the memory is free."""
     field = workspace_size(prob, L.DOP_OP_PSF)
-    g = 1 if save_fields else max(1, min(int(group), prob.k))
+    g = 1 if save_fields else max(1, min(int(group), prob.k, ctx.group_cap.get(field, 4)))
+    if g > 1:
+        # what the device could hold: free memory, blocks torch keeps cached,
+        # and this stream's workspace (replaced below), less a margin
+        free, _ = torch.cuda.mem_get_info(ctx.device)
+        spare = torch.cuda.memory_reserved(ctx.device) - torch.cuda.memory_allocated(ctx.device)
+        budget = free + spare + ctx.workspace_bytes(stream) - (4 << 30)
+        g = max(1, min(g, budget // field))
     while g > 1:
         try:
             return ctx.workspace(g * field, stream), g * field
         except torch.cuda.OutOfMemoryError:
-            ctx.release_workspaces()
-            torch.cuda.empty_cache()
-            g //= 2
+            g -= 1
+            ctx.group_cap[field] = g  # do not try the larger group again
     return ctx.workspace(field, stream), field
 
 

@@ -756,6 +756,9 @@ struct TablePlan {
   // pass-A / A' run and threads (0: 16 columns, about 8 points per thread);
   // the 28,800 grid's 450 x 16 tiles take 512 threads, so two blocks share a CU
   int ra = 0, ta = 0;
+  // pass-B / B' threads (0: about 8 points per thread); the 40,000 grid's
+  // B, B' and C tiles take 512 threads, so two blocks share a CU
+  int tb = 0;
 };
 constexpr int kTabBase = 100;
 constexpr int kNumTab = 14;
@@ -765,8 +768,8 @@ __host__ __device__ constexpr TablePlan table_plan(int i) {
          : i == 2  ? TablePlan{45, 32, 45, 32}        // 1440^2
          : i == 3  ? TablePlan{48, 64, 48, 64}        // 3072^2
          : i == 4  ? TablePlan{225, 16, 15, 240}      // 3600^2
-         : i == 5  ? TablePlan{450, 64, 120, 240, 0, 0, 0, 512}  // 28800^2, 2^7 3^2 5^2
-         : i == 6  ? TablePlan{625, 64, 100, 400}     // 40000^2, 2^6 5^4
+         : i == 5  ? TablePlan{450, 64, 120, 240, 0, 0, 0, 512}         // 28800^2, 2^7 3^2 5^2
+         : i == 6  ? TablePlan{625, 64, 100, 400, 0, 512, 0, 0, 512}    // 40000^2, 2^6 5^4
          : i == 7  ? TablePlan{134, 16, 16, 134}      // 2144^2, 2^5 67
          : i == 8  ? TablePlan{15, 16, 45, 16}        // 720 rows x 240 columns
          : i == 9  ? TablePlan{128, 16, 16, 32}       // 512 x 2048
@@ -798,7 +801,7 @@ struct Plan {
   // (other M: about 8 points per thread, since their mixed-radix stage
   // shapes do not divide evenly among threads and need more registers each)
   static constexpr int TA = TP.ta ? TP.ta : round64(cmin(1024, cmax(64, AX * RA / (POW2 ? 16 : 8))));
-  static constexpr int TB = !POW2 ? round64(cmin(1024, cmax(64, BX * AY / 8)))
+  static constexpr int TB = TP.tb ? TP.tb : !POW2 ? round64(cmin(1024, cmax(64, BX * AY / 8)))
                             : BX * AY > 8192 ? 1024 : threads_for(BX * AY);
   static constexpr int TC = TP.tc ? TP.tc : !POW2 ? round64(cmin(1024, cmax(64, BY * RC / 8)))
                             : BY * RC > 8192 ? 1024 : threads_for(BY * RC);

@@ -293,8 +293,15 @@ dop_status dop_serve_create(dop_context *ctx, void *arena, size_t arena_bytes,
 
 /*
  * Queue a PSF request.  `prob` and its host arrays are copied.  `h` (N x N
- * float32), `amp` (N x N float32 or NULL) and `psf` (output, as dop_psf)
- * are device buffers that must stay alive until the ticket completes.
+ * float32, or the coarse design when prob->upsample >= 2), `amp` (N x N
+ * float32 or NULL; an addition to the serving calls of the paper-derived
+ * boundary, so that aperture-masked requests can be served) and `psf`
+ * (output, as dop_psf) are device buffers that must stay alive until the
+ * ticket completes.  The server runs the request on streams of its own that
+ * are not ordered after any stream of the caller: `h` and `amp` must already
+ * hold their final values when dop_serve_submit is called (complete, e.g.
+ * synchronise, the work that produces them first), and nothing may read or
+ * write `psf` until the ticket is done.
  * DOP_ERR_BUDGET if the request could never fit the arena.
  */
 dop_status dop_serve_submit(dop_server *srv, const dop_problem *prob,

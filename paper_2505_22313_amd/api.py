@@ -405,6 +405,9 @@ class Server:
             if amp is not None:
                 _need(amp, "amp", torch.float32, prob.doe_shape, dev)
             hp, ap, op = _ptr(h), _ptr(amp), _ptr(out)
+            # the server's streams are not ordered after the caller's: let the
+            # work that produced h / amp (and last used out) finish first
+            torch.cuda.current_stream(dev).synchronize()
         check(lib().dop_serve_submit(self.handle, prob.ptr(), hp, ap, op, ctypes.byref(t)),
               "dop_serve_submit")
         self._keep[t.value] = (prob, h, out, amp)

@@ -2,7 +2,7 @@
 #ifndef DOP_HOST_H_
 #define DOP_HOST_H_
 
-#include <hip/hip_runtime.h>
+#include <hip/hip_runtime_api.h>
 
 #include "../../include/dop.h"
 

@@ -8,7 +8,7 @@
 // requests while others are still running, so the passes of several requests
 // overlap on the device.  Results do not depend on what runs beside them:
 // every kernel is deterministic and each request has its own workspace.
-#include <hip/hip_runtime.h>
+#include <hip/hip_runtime_api.h>
 
 #include <algorithm>
 #include <atomic>

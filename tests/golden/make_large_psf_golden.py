@@ -11,10 +11,17 @@ maximum over the crop (float64).
     psf_large_3lam_rows.npz    the sum over 400, 550 and 700 nm (the ends and
                                the middle of the band; at 700 nm the corner
                                bins come within 2 % of the evanescent edge)
+    psf_large_4lam_rows.npz    the sum over 400, 500, 600 and 700 nm: one
+                               whole wavelength group of four, as the timed
+                               configuration runs it
+    psf_large_5lam_rows.npz    the sum over 400, 500, 550, 600 and 700 nm: a
+                               group of four followed by a single wavelength
 
 Needs about 90 GB of host memory (one complex128 65536^2 array plus blocks):
 
-    python tests/golden/make_large_psf_golden.py [out_dir]   (a minute per wavelength)
+    python tests/golden/make_large_psf_golden.py [out_dir] [name ...]
+                                     (a minute per wavelength; names select
+                                      files of SETS, default all)
 """
 
 import os
@@ -30,7 +37,9 @@ import oracle  # noqa: E402
 from oracle import asm  # noqa: E402
 from paper_2505_22313_amd import workloads as wl  # noqa: E402
 
-SETS = {"psf_large_550nm_rows.npz": [15], "psf_large_3lam_rows.npz": [0, 15, 30]}
+SETS = {"psf_large_550nm_rows.npz": [15], "psf_large_3lam_rows.npz": [0, 15, 30],
+        "psf_large_4lam_rows.npz": [0, 10, 20, 30],
+        "psf_large_5lam_rows.npz": [0, 10, 15, 20, 30]}
 
 
 def rows_of(n):
@@ -39,7 +48,11 @@ def rows_of(n):
                     dtype=np.int64)
 
 
-def main(out_dir):
+def main(out_dir, names=None):
+    sets = {k: v for k, v in SETS.items() if not names or k in names}
+    unknown = set(names or ()) - set(SETS)
+    if unknown:
+        raise SystemExit(f"unknown golden(s) {sorted(unknown)}; known: {sorted(SETS)}")
     asm.WORKERS = min(16, os.cpu_count() or 1)
     t0 = time.time()
 
@@ -51,12 +64,13 @@ def main(out_dir):
     log(f"heights {h.shape} {h.dtype}")
     rows = rows_of(p["n"])
     psf = {}
-    for k in sorted({k for ks in SETS.values() for k in ks}):
+    for k in sorted({k for ks in sets.values() for k in ks}):
         log(f"lambda {p['lams'][k]}")
         psf[k] = oracle.psf_lowmem(h, p["dx"], p["z"], p["m"], float(p["lams"][k]),
                                    float(p["n_index"][k]), log=log)
-    for name, ks in SETS.items():
+    for name, ks in sets.items():
         acc = psf[ks[0]] if len(ks) == 1 else sum(psf[k] for k in ks)  # k order
+        # the wavelengths are 400 + 10 k nm
         np.savez(os.path.join(out_dir, name), rows=rows, psf_rows=acc[rows].astype(np.float32),
                  total=np.float64(acc.sum()), peak=np.float64(acc.max()), n=p["n"], m=p["m"],
                  dx=p["dx"], z=p["z"], lams=np.array([p["lams"][k] for k in ks]),
@@ -65,4 +79,4 @@ def main(out_dir):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else HERE)
+    main(sys.argv[1] if len(sys.argv) > 1 else HERE, sys.argv[2:])

@@ -14,6 +14,7 @@ import pytest
 import oracle
 from oracle import asm
 from paper_2505_22313_amd import workloads as wl
+from _close import assert_close, FIELD_ELEM, GRAD_ELEM, INTENSITY_ELEM
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -72,7 +73,7 @@ def test_propagate_matches_oracle(api, m, n, dx, lam, z, out_mode):
     prob = api.Problem(n, m, dx, z, [lam], [1.5], out_mode=out_mode)
     got = api.propagate(dev(u, torch.complex64), prob).cpu().numpy()
     want = oracle.propagate(u.astype(np.complex128), m, dx, lam, z, out_mode=out_mode)
-    assert rel(got, want) < FIELD_TOL
+    assert_close(got, want, FIELD_TOL, FIELD_ELEM)
 
 
 def test_small_workload_psf(api):
@@ -83,8 +84,8 @@ def test_small_workload_psf(api):
     got, saved = api.psf(dev(h, torch.float32), prob, save_fields=True)
     want, fields = oracle.psf(h, p["dx"], p["z"], p["m"], p["lams"], p["n_index"],
                               return_fields=True)
-    assert rel(got.cpu().numpy(), want) < INTENSITY_TOL
-    assert rel(saved[0].cpu().numpy(), fields[0]) < FIELD_TOL
+    assert_close(got.cpu().numpy(), want, INTENSITY_TOL, INTENSITY_ELEM)
+    assert_close(saved[0].cpu().numpy(), fields[0], FIELD_TOL, FIELD_ELEM)
 
 
 def test_field_4096(api):
@@ -97,8 +98,8 @@ def test_field_4096(api):
     got, saved = api.psf(dev(h, torch.float32), prob, save_fields=True)
     want, fields = oracle.psf(h, dx, z, m, lams, nidx, return_fields=True)
     for k in range(2):
-        assert rel(saved[k].cpu().numpy(), fields[k]) < FIELD_TOL
-    assert rel(got.cpu().numpy(), want) < INTENSITY_TOL
+        assert_close(saved[k].cpu().numpy(), fields[k], FIELD_TOL, FIELD_ELEM)
+    assert_close(got.cpu().numpy(), want, INTENSITY_TOL, INTENSITY_ELEM)
 
 
 @pytest.mark.parametrize("out_mode", ["crop", "full"])
@@ -112,7 +113,7 @@ def test_psf_weights_amp_multi_lambda(api, out_mode):
     prob = api.Problem(n, m, dx, z, lams, nidx, weights=w, out_mode=out_mode)
     got = api.psf(dev(h, torch.float32), prob, amp=dev(amp, torch.float32)).cpu().numpy()
     want = oracle.psf(h, dx, z, m, lams, nidx, weights=w, amp=amp, out_mode=out_mode)
-    assert rel(got, want) < INTENSITY_TOL
+    assert_close(got, want, INTENSITY_TOL, INTENSITY_ELEM)
 
 
 def test_evanescent_cut_energy(api):
@@ -123,7 +124,7 @@ def test_evanescent_cut_energy(api):
     prob = api.Problem(n, m, dx, z, [lam], [1.46], out_mode="full")
     got = api.psf(dev(h, torch.float32), prob).cpu().numpy().astype(np.float64)
     want = oracle.psf(h, dx, z, m, [lam], [1.46], out_mode="full")
-    assert rel(got, want) < INTENSITY_TOL
+    assert_close(got, want, INTENSITY_TOL, INTENSITY_ELEM)
     assert abs(got.sum() / want.sum() - 1) < 1e-5
     assert want.sum() < n * n * 0.999
 
@@ -142,7 +143,7 @@ def test_backward_matches_oracle(api):
     _, saved = api.psf(hd, prob, amp=ad, save_fields=True)
     got = api.psf_backward(hd, prob, saved, dev(g, torch.float32), amp=ad).cpu().numpy()
     want = oracle.psf_backward(h, dx, z, m, lams, nidx, g, weights=w, amp=amp)
-    assert rel(got, want) < GRAD_TOL
+    assert_close(got, want, GRAD_TOL, GRAD_ELEM)
 
 
 def test_autograd_function(api):
@@ -161,7 +162,7 @@ def test_autograd_function(api):
     p = oracle.psf(h, dx, z, m, lams, nidx)
     g = 2.0 * (p - target) / (n * n)
     want = oracle.psf_backward(h, dx, z, m, lams, nidx, g)
-    assert rel(hd.grad.cpu().numpy(), want) < GRAD_TOL
+    assert_close(hd.grad.cpu().numpy(), want, GRAD_TOL, GRAD_ELEM)
     assert abs(loss.item() / np.mean((p - target) ** 2) - 1) < 1e-5
 
 
@@ -187,7 +188,7 @@ def test_mid_workload_psf(api):
     for k in range(3):
         print(f"  oracle lambda {p['lams'][k]}", flush=True)
         want += oracle.psf(h, p["dx"], p["z"], p["m"], [p["lams"][k]], [p["n_index"][k]])
-    assert rel(got, want) < 1e-4
+    assert_close(got, want, 1e-4, 1e-4)
 
 
 # Band-limited ASM: z large against M dx so that f_lim falls well inside the
@@ -212,7 +213,7 @@ def test_propagate_bandlimit_matches_oracle(api, m, n, dx, lam, z, out_mode):
     got = api.propagate(dev(u, torch.complex64), prob).cpu().numpy()
     want = oracle.propagate(u.astype(np.complex128), m, dx, lam, z, out_mode=out_mode,
                             bandlimit=True)
-    assert rel(got, want) < FIELD_TOL
+    assert_close(got, want, FIELD_TOL, FIELD_ELEM)
     plain = oracle.propagate(u.astype(np.complex128), m, dx, lam, z, out_mode=out_mode)
     assert rel(plain, want) > 1e-3
 
@@ -229,10 +230,10 @@ def test_psf_and_backward_bandlimit(api):
     hd = dev(h, torch.float32)
     got, saved = api.psf(hd, prob, save_fields=True)
     want = oracle.psf(h, dx, z, m, lams, nidx, weights=w, bandlimit=True)
-    assert rel(got.cpu().numpy(), want) < INTENSITY_TOL
+    assert_close(got.cpu().numpy(), want, INTENSITY_TOL, INTENSITY_ELEM)
     gh = api.psf_backward(hd, prob, saved, dev(g, torch.float32)).cpu().numpy()
     want_g = oracle.psf_backward(h, dx, z, m, lams, nidx, g, weights=w, bandlimit=True)
-    assert rel(gh, want_g) < GRAD_TOL
+    assert_close(gh, want_g, GRAD_TOL, GRAD_ELEM)
 
 
 def test_hip_graph_capture_replays(api):

@@ -18,6 +18,7 @@ import oracle
 from oracle import asm
 from oracle import upsample as ups
 from paper_2505_22313_amd import workloads as wl
+from _close import assert_close, FIELD_ELEM, GRAD_ELEM, INTENSITY_ELEM
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -36,10 +37,6 @@ def api():
     from paper_2505_22313_amd import api as _api
     yield _api
     torch.cuda.empty_cache()
-
-
-def rel(a, b):
-    return float(np.linalg.norm((np.asarray(a) - b).ravel()) / np.linalg.norm(np.ravel(b)))
 
 
 def dev(x, dtype):
@@ -70,7 +67,7 @@ def test_rect_propagate_matches_oracle(api, my, mx, ny, nx, dx, lam, z, out_mode
     got = api.propagate(dev(u, torch.complex64), prob).cpu().numpy()
     want = oracle.propagate(u.astype(np.complex128), (my, mx), dx, lam, z, out_mode=out_mode)
     assert got.shape == want.shape
-    assert rel(got, want) < FIELD_TOL
+    assert_close(got, want, FIELD_TOL, FIELD_ELEM)
 
 
 @pytest.mark.parametrize("my,mx,ny,nx", [(720, 240, 360, 120), (240, 2144, 200, 1500),
@@ -89,10 +86,10 @@ def test_rect_psf_and_backward(api, my, mx, ny, nx):
     hd, ad = dev(h, torch.float32), dev(amp, torch.float32)
     got, saved = api.psf(hd, prob, amp=ad, save_fields=True)
     want = oracle.psf(h, dx, z, (my, mx), lams, nidx, weights=w, amp=amp)
-    assert rel(got.cpu().numpy(), want) < INTENSITY_TOL
+    assert_close(got.cpu().numpy(), want, INTENSITY_TOL, INTENSITY_ELEM)
     gh = api.psf_backward(hd, prob, saved, dev(g, torch.float32), amp=ad).cpu().numpy()
     want_g = oracle.psf_backward(h, dx, z, (my, mx), lams, nidx, g, weights=w, amp=amp)
-    assert rel(gh, want_g) < GRAD_TOL
+    assert_close(gh, want_g, GRAD_TOL, GRAD_ELEM)
 
 
 @pytest.mark.parametrize("my,mx,ny,nx,z", [(5360, 240, 2000, 200, 4000.0),
@@ -106,7 +103,7 @@ def test_rect_full_output_and_bandlimit(api, my, mx, ny, nx, z):
     got = api.psf(dev(h, torch.float32), prob).cpu().numpy()
     want = oracle.psf(h, dx, z, (my, mx), [lam], [1.46], out_mode="full", bandlimit=True)
     assert got.shape == (my, mx)
-    assert rel(got, want) < INTENSITY_TOL
+    assert_close(got, want, INTENSITY_TOL, INTENSITY_ELEM)
 
 
 def test_rect_fused_nearest_upsampling(api):
@@ -123,12 +120,12 @@ def test_rect_fused_nearest_upsampling(api):
     assert prob.h_shape == (100, 50)
     hd = dev(hc, torch.float32)
     got, saved = api.psf(hd, prob, save_fields=True)
-    assert rel(got.cpu().numpy(), oracle.psf(hf, dx, z, (my, mx), lams, nidx)) < INTENSITY_TOL
+    assert_close(got.cpu().numpy(), oracle.psf(hf, dx, z, (my, mx), lams, nidx), INTENSITY_TOL, INTENSITY_ELEM)
     gc = api.psf_backward(hd, prob, saved, dev(g, torch.float32)).cpu().numpy()
     want = oracle.psf_backward(hf, dx, z, (my, mx), lams, nidx, g)
     want_c = want.reshape(100, s, 50, s).sum(axis=(1, 3))
     assert gc.shape == (100, 50)
-    assert rel(gc, want_c) < GRAD_TOL
+    assert_close(gc, want_c, GRAD_TOL, GRAD_ELEM)
 
 
 @pytest.mark.timeout(300)
@@ -144,5 +141,5 @@ def test_rect_paper_digit_split_whole_psf(api):
     got = api.psf(dev(h, torch.float32), prob).double().cpu().numpy()
     torch.cuda.empty_cache()
     want = oracle.psf(h, dx, z, (my, mx), lams, nidx)
-    assert rel(got, want) < 1e-4
+    assert_close(got, want, 1e-4, 1e-4)
     assert abs(got.sum() / want.sum() - 1) < 1e-5

@@ -14,6 +14,7 @@ import pytest
 import oracle
 from oracle import asm
 from paper_2505_22313_amd import workloads as wl
+from _close import assert_close, INTENSITY_ELEM
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -74,7 +75,7 @@ def test_serve_bitwise_alone_vs_mix(api):
         want = oracle.psf(h.cpu().numpy(), prob.dx, prob.z, prob.m, prob.lambdas, prob.n_index,
                           amp=None if amp is None else amp.cpu().numpy(), out_mode=prob.out_mode)
         got = alone[i].cpu().numpy()
-        assert np.linalg.norm(got - want) / np.linalg.norm(want) < 2e-5
+        assert_close(got, want, 2e-5, INTENSITY_ELEM, f"request {i}")
 
 
 def test_serve_many_small_requests_overlap(api):
@@ -153,4 +154,61 @@ def test_serve_mixed_problem_kinds(api):
         hf = ups.upsample(h, 8, "nearest") if prob.upsample > 1 else h
         want = oracle.psf(hf, prob.dx, prob.z, prob.grid_shape, prob.lambdas, prob.n_index,
                           out_mode=prob.out_mode, bandlimit=prob.bandlimit)
-        assert np.linalg.norm(alone[i].cpu().numpy() - want) / np.linalg.norm(want) < 2e-5
+        assert_close(alone[i].cpu().numpy(), want, 2e-5, INTENSITY_ELEM, f"request {i}")
+
+
+@pytest.mark.timeout(900)
+def test_serve_serving_workload_sizes(api):
+    """Requests at the serving workload's sizes: N in {2048, 4096, 8192,
+    16384} on 2x-padded grids, 1..31 wavelengths over 400..700 nm, z in
+    [5, 50] mm, smooth random heights, through a 4-slot server whose arena
+    (about 26 GB) holds three of the largest workspaces, so admission waits
+    for memory as well as slots.  Every result is bitwise the same alone and
+    in the mix; the N = 2048 requests (one with all 31 wavelengths) are also
+    checked against the FP64 oracle."""
+    rng = np.random.default_rng(55)
+    sizes = [2048, 16384, 4096, 8192, 2048, 16384, 8192, 4096]
+    ks = [31, 31, 17, 24, 3, 9, 1, 12]
+    pools = {n: torch.from_numpy(wl.serve_height_pool(n, count=1, seed=55)[0]).cuda()
+             for n in set(sizes)}
+    reqs = []
+    for i, (n, k) in enumerate(zip(sizes, ks)):
+        lams = np.array([0.55]) if k == 1 else np.linspace(0.40, 0.70, k)
+        mode = "full" if i == 7 else "crop"
+        prob = api.Problem(n, 2 * n, 1.0, float(rng.uniform(5000.0, 50000.0)), lams,
+                           wl.cauchy_index(lams), out_mode=mode)
+        reqs.append((prob, pools[n]))
+    print("  alone", flush=True)
+    alone = [api.psf(h, prob).clone() for prob, h in reqs]
+    torch.cuda.synchronize()
+    api.default_context(0).release_workspaces()
+    torch.cuda.empty_cache()
+    big = max(api.workspace_size(p) for p, _ in reqs)
+    srv = api.Server(3 * big, max_slots=4)
+    try:
+        outs = [torch.full(p.out_shape, float("nan"), device="cuda") for p, _ in reqs]
+        torch.cuda.synchronize()
+        print("  mix", flush=True)
+        tickets = [srv.submit(p, h, o) for (p, h), o in zip(reqs, outs)]
+        peak = 0
+        while srv.stats()["completed"] < len(reqs):
+            peak = max(peak, srv.stats()["running"])
+        for t in tickets:
+            srv.wait(t, 120.0)
+        stats = srv.stats()
+        assert stats["completed"] == len(reqs) and stats["failed"] == 0
+        assert stats["arena_peak"] <= 3 * big
+        assert peak >= 2
+        for i, (a, b) in enumerate(zip(alone, outs)):
+            assert torch.equal(a, b), f"request {i} (N {sizes[i]}, k {ks[i]}) differs"
+    finally:
+        srv.close()
+        del outs
+        torch.cuda.empty_cache()
+    for i, (prob, h) in enumerate(reqs):
+        if prob.n != 2048:
+            continue
+        print(f"  oracle request {i}: k {prob.k}", flush=True)
+        want = oracle.psf(h.cpu().numpy(), prob.dx, prob.z, prob.m, prob.lambdas, prob.n_index,
+                          out_mode=prob.out_mode)
+        assert_close(alone[i].cpu().numpy(), want, 2e-5, INTENSITY_ELEM, f"request {i}")

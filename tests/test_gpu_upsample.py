@@ -19,6 +19,7 @@ import oracle
 from oracle import asm
 from oracle import upsample as ups
 from paper_2505_22313_amd import workloads as wl
+from _close import assert_close, GRAD_ELEM, INTENSITY_ELEM
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -35,10 +36,6 @@ def api():
         pytest.skip("no GPU")
     from paper_2505_22313_amd import api as _api
     return _api
-
-
-def rel(a, b):
-    return float(np.linalg.norm((np.asarray(a) - b).ravel()) / np.linalg.norm(np.ravel(b)))
 
 
 def dev(x):
@@ -60,7 +57,7 @@ def test_upsample_matches_oracle(api, nc, s, kind):
     if kind == "nearest":
         assert np.array_equal(got, want.astype(np.float32))
     else:
-        assert rel(got, want) < 1e-6
+        assert_close(got, want, 1e-6, 1e-6)
 
 
 @pytest.mark.parametrize("nc,s", SIZES)
@@ -70,7 +67,7 @@ def test_upsample_adjoint_matches_oracle(api, nc, s, kind):
     g = rng.standard_normal((nc * s, nc * s)).astype(np.float32)
     got = api.upsample_adjoint(dev(g), s, kind).cpu().numpy()
     want = ups.upsample_adjoint(g, s, kind)
-    assert rel(got, want) < 1e-5
+    assert_close(got, want, 1e-5, 1e-5)
 
 
 def test_lanczos_large_sampled_rows(api):
@@ -83,7 +80,7 @@ def test_lanczos_large_sampled_rows(api):
     w = ups.axis_matrix(nc, s, "lanczos3")
     want = (w[rows] @ hc.astype(np.float64)) @ w.T
     got = fine[torch.tensor(rows, device="cuda")].cpu().numpy()
-    assert rel(got, want) < 1e-6
+    assert_close(got, want, 1e-6, 1e-6)
     del fine
     torch.cuda.empty_cache()
 
@@ -107,7 +104,7 @@ def test_fused_nearest_psf_and_backward(api):
     pf = api.Problem(n, m, dx, z, lams, nidx)
     got, saved = api.psf(dev(hc), pu, amp=ad, save_fields=True)
     want = oracle.psf(hf, dx, z, m, lams, nidx, amp=amp)
-    assert rel(got.cpu().numpy(), want) < INTENSITY_TOL
+    assert_close(got.cpu().numpy(), want, INTENSITY_TOL, INTENSITY_ELEM)
     hf_dev = api.upsample(dev(hc), s, "nearest")
     ref, saved_ref = api.psf(hf_dev, pf, amp=ad, save_fields=True)
     assert torch.equal(got, ref) and torch.equal(saved, saved_ref)
@@ -115,7 +112,7 @@ def test_fused_nearest_psf_and_backward(api):
     assert tuple(gc.shape) == (nc, nc)
     want_g = ups.upsample_adjoint(oracle.psf_backward(hf, dx, z, m, lams, nidx, g, amp=amp), s,
                                   "nearest")
-    assert rel(gc.cpu().numpy(), want_g) < GRAD_TOL
+    assert_close(gc.cpu().numpy(), want_g, GRAD_TOL, GRAD_ELEM)
     gf = api.psf_backward(hf_dev, pf, saved_ref, dev(g), amp=ad)
     assert torch.equal(gc, api.upsample_adjoint(gf, s, "nearest"))
 
@@ -140,7 +137,7 @@ def test_lanczos_design_gradient_through_autograd(api):
     p = oracle.psf(hf, dx, z, m, lams, nidx)
     gpsf = 2.0 * (p - target) / (n * n)
     want = ups.upsample_adjoint(oracle.psf_backward(hf, dx, z, m, lams, nidx, gpsf), s, "lanczos3")
-    assert rel(hcd.grad.cpu().numpy(), want) < GRAD_TOL
+    assert_close(hcd.grad.cpu().numpy(), want, GRAD_TOL, GRAD_ELEM)
 
 
 # (ncy, ncx, s): rectangular designs, one-sample axes, fine axes that are not
@@ -159,11 +156,11 @@ def test_rect_upsample_and_adjoint_match_oracle(api, ncy, ncx, s, kind):
     if kind == "nearest":
         assert np.array_equal(got, want.astype(np.float32))
     else:
-        assert rel(got, want) < 1e-6
+        assert_close(got, want, 1e-6, 1e-6)
     g = rng.standard_normal((ncy * s, ncx * s)).astype(np.float32)
     got_a = api.upsample_adjoint(dev(g), s, kind).cpu().numpy()
     assert got_a.shape == (ncy, ncx)
-    assert rel(got_a, ups.upsample_adjoint(g, s, kind)) < 1e-5
+    assert_close(got_a, ups.upsample_adjoint(g, s, kind), 1e-5, 1e-5)
 
 
 def test_rect_lanczos_design_gradient_through_autograd(api):
@@ -186,4 +183,4 @@ def test_rect_lanczos_design_gradient_through_autograd(api):
     gpsf = 2.0 * (p - target) / (ny * nx)
     want = ups.upsample_adjoint(oracle.psf_backward(hf, dx, z, (my, mx), lams, nidx, gpsf), s,
                                 "lanczos3")
-    assert rel(hcd.grad.cpu().numpy(), want) < GRAD_TOL
+    assert_close(hcd.grad.cpu().numpy(), want, GRAD_TOL, GRAD_ELEM)

@@ -215,7 +215,9 @@ def test_circular_lens_focus_airy():
 # ---------------------------------------------------------------------------
 
 def _loss_setup(out_mode):
-    n, m, dx, z = 32, 64, 1.0, 1500.0
+    # the differentiable-design gradcheck instance: 64 x 64 heights on a
+    # 128 x 128 grid, three wavelengths, FP64
+    n, m, dx, z = 64, 128, 1.0, 1500.0
     lams = np.array([0.45, 0.55, 0.65])
     nidx = wl.cauchy_index(lams)
     w = np.array([1.0, 0.7, 1.3])
@@ -252,6 +254,27 @@ def test_gradient_finite_differences(out_mode):
         e[i, j] = 1.0
         fd = (loss(h + eps * e) - loss(h - eps * e)) / (2 * eps)
         assert abs(fd - g[i, j]) <= 1e-6 * np.max(np.abs(g)) + 1e-8 * abs(fd)
+
+
+@pytest.mark.slow
+def test_gradient_full_gradcheck_64():
+    """Central finite differences of the loss with respect to every one of
+    the 64 x 64 heights (step 1e-5 in FP64) against the adjoint gradient,
+    element by element."""
+    h, loss, grad, _ = _loss_setup("crop")
+    g = grad(h)
+    eps = 1e-5
+    fd = np.empty_like(h)
+    for i in range(h.shape[0]):
+        for j in range(h.shape[1]):
+            hp = h.copy()
+            hp[i, j] += eps
+            lp = loss(hp)
+            hp[i, j] -= 2 * eps
+            fd[i, j] = (lp - loss(hp)) / (2 * eps)
+    scale = np.max(np.abs(g))
+    assert np.max(np.abs(fd - g)) <= 1e-8 * scale + 1e-12
+    assert np.linalg.norm(fd - g) <= 1e-8 * np.linalg.norm(g)
 
 
 def test_adjoint_dot_product():

@@ -137,11 +137,13 @@ def _pct(v, q):
     return v[i] * (1 - f) + v[min(i + 1, len(v) - 1)] * f
 
 
-def serve_measure(api, wl, torch, count, rate_hz, pool, slots=4, seed=5):
-    """Replay a Poisson trace of PSF requests twice on the same GPU: through
-    the continuous-batching server (`slots` concurrent requests, arena for
-    `slots` of the largest workspaces) and one request at a time on one
-    stream (the plain path).  Latency = completion - arrival."""
+def serve_measure(api, wl, torch, count, rate_hz, pool, slots=4, seed=5,
+                  policies=("chunked", "fifo")):
+    """Replay a Poisson trace of PSF requests on the same GPU: one request at
+    a time on one stream (the plain path, dop_psf with wavelength groups),
+    then through the continuous-batching server under each policy (`slots`
+    admitted requests, an arena of 2 * slots of the largest one-field
+    workspaces).  Latency = completion - arrival."""
     import threading
     trace = wl.serve_trace(count, rate_hz, seed=seed, sizes=tuple(sorted(pool)))
     reqs = []
@@ -163,12 +165,14 @@ def serve_measure(api, wl, torch, count, rate_hz, pool, slots=4, seed=5):
         torch.cuda.synchronize()
         lat_seq.append((time.perf_counter() - t0 - ta) * 1e3)
     span_seq = time.perf_counter() - t0
+    api.default_context().release_workspaces()
+    torch.cuda.empty_cache()
 
-    # continuous batching, under each admission policy
+    # continuous batching, under each policy
     big = max(api.workspace_size(p) for _, p, _ in reqs)
 
     def served(policy):
-        srv = api.Server(slots * big, max_slots=slots, policy=policy)
+        srv = api.Server(2 * slots * big, max_slots=slots, policy=policy)
         tickets = [None] * len(reqs)
         t0 = time.perf_counter()
 
@@ -192,15 +196,15 @@ def serve_measure(api, wl, torch, count, rate_hz, pool, slots=4, seed=5):
                 "throughput_req_s": round(count / span, 2),
                 "mpix_lambda_s": round(work / span, 1), "arena_peak_gb": round(peak / 1e9, 2)}
 
-    res_fifo = served("fifo")
-    res_size = served("size_aware")
+    res = {pol: served(pol) for pol in policies}
     del outs
     torch.cuda.synchronize()
     return {
         "requests": count, "offered_rate_hz": round(rate_hz, 2), "slots": slots,
         "mpix_lambda": round(work, 1),
-        "served": res_fifo,
-        "served_size_aware": res_size,
+        "served": res[policies[0]],
+        "policy": policies[0],
+        **{f"served_{pol}": res[pol] for pol in policies[1:]},
         "sequential": {"p50_ms": round(_pct(lat_seq, 0.5), 2),
                        "p99_ms": round(_pct(lat_seq, 0.99), 2),
                        "throughput_req_s": round(count / span_seq, 2),
@@ -293,6 +297,24 @@ def copy_ceiling_gbs(torch, nbytes=1 << 32):
     ms = _event_ms(torch, lambda: dst.copy_(src), 5)
     del src, dst
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def ceilings_measure(api, torch, ws, m, stream_bytes=16 << 30):
+    """Measured HBM ceilings (dop_probe_bandwidth) on the workspace memory
+    itself: 16-byte non-temporal stream kernels over 16 GiB (read, write,
+    copy, in-place read+write) and pass C's access pattern without its
+    arithmetic on the m x m field.  GB/s of bytes moved, HIP-event timed."""
+    out = {}
+    for kind in ("read", "write", "copy", "inplace"):
+        moved = api.probe_bandwidth(kind, ws, stream_bytes)
+        ms = _event_ms(torch, lambda: api.probe_bandwidth(kind, ws, stream_bytes), 5)
+        out[kind] = round(moved / (ms * 1e-3) / 1e9, 1)
+    if m >= 16384 and m & (m - 1) == 0:
+        moved = api.probe_bandwidth("passc", ws, m=m)
+        ms = _event_ms(torch, lambda: api.probe_bandwidth("passc", ws, m=m), 5)
+        out["passc_pattern"] = round(moved / (ms * 1e-3) / 1e9, 1)
+        out["passc_pattern_ms"] = round(ms, 3)
+    return out
 
 
 def other_workloads_measure(api, wl, torch, ctx):
@@ -450,7 +472,11 @@ def main():
     ap.add_argument("--group", type=int, default=4,
                     help="wavelengths per group in the timed PSF calls (1 = one at a time)")
     ap.add_argument("--no-design", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-requests", type=int, default=400,
+                    help="requests in the trace at 0.7 x capacity (the 200 req/s trace, "
+                         "about 11 x overload, uses a quarter of them)")
+    ap.add_argument("--serve-policies", default="chunked,fifo",
+                    help="server policies to replay, the first reported as 'served'")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the upsampling / band-limit measurements")
     ap.add_argument("--calib-copy", action="store_true",
@@ -530,6 +556,11 @@ def main():
     sumv = float(psf.double().sum().item())
     copy_gbs = copy_ceiling_gbs(torch)
     log(f"device copy ceiling {copy_gbs:.0f} GB/s")
+    ceil = ceilings_measure(api, torch, ctx.workspace(0, torch.cuda.current_stream().cuda_stream),
+                            m if mx == my else 0)
+    log(f"probe ceilings (GB/s): {ceil}")
+    ceiling = ceil["inplace"]
+    pattern = ceil.get("passc_pattern") if dom == "pass_c" else None
 
     line = {
         "metric": METRIC,
@@ -574,6 +605,11 @@ def main():
             "traffic_gbs": None if traffic is None else round(traffic / (dp["avg_ms"] * 1e-3) / 1e9, 1),
             "copy_ceiling_gbs": round(copy_gbs, 1),
             "frac_of_copy": round(achieved / copy_gbs, 4),
+            "ceiling_gbs": ceiling,
+            "frac_of_ceiling": round(achieved / ceiling, 4),
+            "pattern_ceiling_gbs": pattern,
+            "frac_of_pattern": None if pattern is None else round(achieved / pattern, 4),
+            "ceilings": ceil,
         },
         "psf_sum": sumv,
     }
@@ -599,11 +635,14 @@ def main():
         log("serving: generating the height pool")
         pool = {n_: [torch.from_numpy(x).cuda() for x in wl.serve_height_pool(n_)]
                 for n_ in (2048, 4096, 8192, 16384)}
+        pols = tuple(args.serve_policies.split(","))
         log("serving: trace at 200 req/s")
-        hot = serve_measure(api, wl, torch, args.serve_requests, 200.0, pool)
+        hot = serve_measure(api, wl, torch, max(8, args.serve_requests // 4), 200.0, pool,
+                            policies=pols)
         cap = hot["sequential"]["throughput_req_s"]
         log(f"serving: trace at 0.7 x capacity ({0.7 * cap:.1f} req/s)")
-        cool = serve_measure(api, wl, torch, args.serve_requests, 0.7 * cap, pool, seed=6)
+        cool = serve_measure(api, wl, torch, args.serve_requests, 0.7 * cap, pool, seed=6,
+                             policies=pols)
         line["serve"] = {"trace": "Poisson arrivals, N in {2048,4096,8192,16384}, M=2N, "
                                   "1-31 wavelengths over 400-700 nm, z in [5,50] mm",
                          "at_200_req_s": hot, "at_0.7x_capacity": cool}

@@ -262,12 +262,44 @@ dop_status dop_profile_enable(dop_context *ctx, int enable);
 dop_status dop_profile_read(dop_context *ctx, dop_pass_profile *out, int max, int *count);
 
 /* ------------------------------------------------------------------------
+ * Bandwidth probes: the HBM ceilings the passes are measured against (the
+ * paper notes that memory, not arithmetic, limits the FFT propagation,
+ * Sec. 4).  Each call enqueues one kernel on `stream` over the caller's
+ * device buffer `buf` (`bytes`, 256-byte aligned, a multiple of 64; its
+ * contents are overwritten) and reports the bytes the kernel moves in
+ * *moved:
+ *   DOP_PROBE_READ     reads every byte of buf              (moved = bytes)
+ *   DOP_PROBE_WRITE    writes every byte                    (moved = bytes)
+ *   DOP_PROBE_COPY     copies the first half onto the second (moved = bytes)
+ *   DOP_PROBE_INPLACE  reads and writes back every byte     (moved = 2 bytes)
+ * with 16-byte accesses and non-temporal hints, and
+ *   DOP_PROBE_PASSC    pass C's access pattern without its arithmetic, on
+ *                      the field of the square power-of-two grid m (16384
+ *                      .. 131072; buf holds 8 m (m + 16) bytes): the same
+ *                      tiles, tile order, grid, prefetch, register layout and
+ *                      LDS footprint, each element read and written back in
+ *                      place                            (moved = 16 m^2).
+ * m is ignored by the stream kinds.  Validated before anything is enqueued.
+ * ---------------------------------------------------------------------- */
+enum {
+  DOP_PROBE_READ = 0,
+  DOP_PROBE_WRITE = 1,
+  DOP_PROBE_COPY = 2,
+  DOP_PROBE_INPLACE = 3,
+  DOP_PROBE_PASSC = 4
+};
+
+dop_status dop_probe_bandwidth(dop_context *ctx, int kind, void *buf, size_t bytes, int m,
+                               size_t *moved, void *stream);
+
+/* ------------------------------------------------------------------------
  * Serving: continuous batching of PSF requests (dop_psf, CROP or FULL) of
  * mixed sizes and wavelength counts.  The server sub-allocates workspaces
  * from a caller-provided device arena (it never calls hipMalloc per request),
- * admits queued requests in FIFO order as slots and arena memory free up, and
- * runs each admitted request on its own stream so that their passes overlap
- * on the GPU.  Thread-safe.
+ * admits queued requests as request slots and arena memory free up, and runs
+ * their work on streams of its own while others are still running (see the
+ * policies below).  Each request's result is bitwise the same as dop_psf on
+ * its own.  Thread-safe.
  * ---------------------------------------------------------------------- */
 
 typedef struct {
@@ -308,21 +340,32 @@ dop_status dop_serve_submit(dop_server *srv, const dop_problem *prob,
                             const float *h, const float *amp, float *psf,
                             uint64_t *ticket);
 
-/* Admission policies.  Both admit in submission order (the head of the queue
- * waits until a slot and arena memory are free).
- *   DOP_SERVE_FIFO (default): the head starts as soon as it fits, beside
- *     whatever runs.
- *   DOP_SERVE_SIZE_AWARE: while requests run, the head starts only if its
- *     work (n_lambda * m^2) is at most share_ratio times the largest running
- *     request's; otherwise it waits for the GPU to drain.  Large requests
- *     then run one after another, each sharing the GPU only with small ones,
- *     which keeps their latency close to running alone while small requests
- *     still start beside them. */
-enum { DOP_SERVE_FIFO = 0, DOP_SERVE_SIZE_AWARE = 1 };
+/* Scheduling policies.
+ *   DOP_SERVE_CHUNKED (default): a request runs in chunks of one wavelength
+ *     group (up to four wavelengths; its workspace holds that many fields,
+ *     at most half the arena, or one field when no more fits at admission).
+ *     All chunks go through one in-order stream, two enqueued at a time;
+ *     each time a chunk completes, the next is taken from the admitted
+ *     request with the least work left (n_lambda not yet enqueued x my x m),
+ *     except that requests older than the age bound (seconds since submit)
+ *     go first, oldest first.  A request arriving while a large one runs
+ *     waits for at most two chunks; the large one pauses but never shares
+ *     the GPU.  Admission takes the head of the queue first; while the head
+ *     does not fit and is younger than the age bound, later requests that
+ *     fit (among the next 32) may be admitted ahead of it.
+ *   DOP_SERVE_FIFO: admission in submission order; a request's whole PSF is
+ *     enqueued at admission on its slot's stream, beside whatever runs.
+ *   DOP_SERVE_SIZE_AWARE: as FIFO, but while requests run the head starts
+ *     only if its work (n_lambda * my * m) is at most share_ratio times the
+ *     largest running request's; otherwise it waits for the GPU to drain. */
+enum { DOP_SERVE_FIFO = 0, DOP_SERVE_SIZE_AWARE = 1, DOP_SERVE_CHUNKED = 2 };
 
-/* Set the admission policy (applies to requests not yet started).
- * share_ratio >= 0 is used by DOP_SERVE_SIZE_AWARE. */
-dop_status dop_serve_set_policy(dop_server *srv, int policy, double share_ratio);
+/* Set the policy for requests not yet admitted (admitted ones finish under
+ * the policy they were admitted with).  `param` (finite, >= 0) is the age
+ * bound in seconds for DOP_SERVE_CHUNKED (default 0.5; 0 serves chunks
+ * oldest request first), share_ratio for DOP_SERVE_SIZE_AWARE (default
+ * 0.25), and ignored for DOP_SERVE_FIFO. */
+dop_status dop_serve_set_policy(dop_server *srv, int policy, double param);
 
 /* DOP_OK when done, DOP_NOT_READY while queued/running, or the request's
  * error.  A finished ticket can be polled any number of times. */
@@ -344,10 +387,12 @@ dop_status dop_serve_destroy(dop_server *srv);
 
 /*
  * Test hook: a server whose executor is a host-side mock instead of the GPU.
- * Each admitted request "runs" for service_us_per_mpix * (K * M^2 / 1e6)
- * microseconds of wall time and writes nothing.  `arena` is only used as an
- * address range (may be any non-NULL value).  For CPU tests of admission,
- * budget, FIFO order and shutdown; needs no GPU.
+ * Its streams are in-order queues of wall time: a chunk of k wavelengths
+ * (a whole request under FIFO / SIZE_AWARE) occupies its stream for
+ * service_us_per_mpix * (k * my * m / 1e6) microseconds and writes nothing.
+ * `arena` is only used as an address range (may be any non-NULL value).
+ * For CPU tests of admission, scheduling, budget, order and shutdown; needs
+ * no GPU.
  */
 dop_status dop_serve_create_mock(void *arena, size_t arena_bytes,
                                  int max_slots, double service_us_per_mpix,

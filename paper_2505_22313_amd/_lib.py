@@ -32,12 +32,18 @@ DOP_UPSAMPLE_LANCZOS3 = 1
 DOP_MAX_UPSAMPLE = 16
 DOP_SERVE_FIFO = 0
 DOP_SERVE_SIZE_AWARE = 1
+DOP_SERVE_CHUNKED = 2
 
 DOP_OUT_CROP = 0
 DOP_OUT_FULL = 1
 DOP_OP_PROPAGATE = 0
 DOP_OP_PSF = 1
 DOP_OP_PSF_BACKWARD = 2
+DOP_PROBE_READ = 0
+DOP_PROBE_WRITE = 1
+DOP_PROBE_COPY = 2
+DOP_PROBE_INPLACE = 3
+DOP_PROBE_PASSC = 4
 
 
 class DopProblem(ctypes.Structure):
@@ -118,6 +124,8 @@ _SIGNATURES = {
                                          ctypes.c_int, _VP, _VP, _VP]),
     "dop_upsample_adjoint_rect": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                  ctypes.c_int, _VP, _VP, _VP]),
+    "dop_probe_bandwidth": (ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_size_t, ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_size_t), _VP]),
     "dop_profile_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
     "dop_profile_read": (ctypes.c_int, [_VP, ctypes.POINTER(DopPassProfile), ctypes.c_int,
                                         ctypes.POINTER(ctypes.c_int)]),

@@ -305,6 +305,26 @@ def psf_autograd(h, prob, amp=None):
     return DopPSF.apply(h, prob, amp)
 
 
+PROBE_KINDS = {"read": L.DOP_PROBE_READ, "write": L.DOP_PROBE_WRITE, "copy": L.DOP_PROBE_COPY,
+               "inplace": L.DOP_PROBE_INPLACE, "passc": L.DOP_PROBE_PASSC}
+
+
+def probe_bandwidth(kind, buf, nbytes=None, m=0, ctx=None):
+    """Enqueue one bandwidth probe (dop_probe_bandwidth) over the first
+    nbytes of the device tensor buf (its contents are overwritten) on the
+    current stream; returns the bytes the kernel moves."""
+    ctx = ctx or default_context(buf.device.index)
+    nbytes = buf.numel() * buf.element_size() if nbytes is None else int(nbytes)
+    if nbytes > buf.numel() * buf.element_size():
+        raise ValueError("nbytes exceeds the buffer")
+    moved = ctypes.c_size_t(0)
+    check(lib().dop_probe_bandwidth(ctx.handle, PROBE_KINDS[kind], _ptr(buf), nbytes, int(m),
+                                    ctypes.byref(moved),
+                                    ctypes.c_void_p(_stream_handle(ctx.device))),
+          "dop_probe_bandwidth")
+    return moved.value
+
+
 UPSAMPLE_KINDS = {"nearest": L.DOP_UPSAMPLE_NEAREST, "lanczos3": L.DOP_UPSAMPLE_LANCZOS3}
 
 
@@ -364,10 +384,11 @@ class DopUpsample(torch.autograd.Function):
 class Server:
     """Continuous-batching PSF server over a device arena (see dop.h)."""
 
-    POLICIES = {"fifo": L.DOP_SERVE_FIFO, "size_aware": L.DOP_SERVE_SIZE_AWARE}
+    POLICIES = {"fifo": L.DOP_SERVE_FIFO, "size_aware": L.DOP_SERVE_SIZE_AWARE,
+                "chunked": L.DOP_SERVE_CHUNKED}
 
     def __init__(self, arena_bytes, max_slots=4, ctx=None, mock_us_per_mpix=None,
-                 policy="fifo", share_ratio=0.25):
+                 policy="chunked", share_ratio=0.25, age_bound_s=0.5):
         self.mock = mock_us_per_mpix is not None
         h = ctypes.c_void_p()
         if self.mock:
@@ -384,11 +405,13 @@ class Server:
                                          int(max_slots), ctypes.byref(h)), "dop_serve_create")
         self.handle = h
         self._keep = {}
-        self.set_policy(policy, share_ratio)
+        self.set_policy(policy, share_ratio=share_ratio, age_bound_s=age_bound_s)
 
-    def set_policy(self, policy, share_ratio=0.25):
-        """Admission policy: "fifo" or "size_aware" (see dop_serve_set_policy)."""
-        check(lib().dop_serve_set_policy(self.handle, self.POLICIES[policy], float(share_ratio)),
+    def set_policy(self, policy, share_ratio=0.25, age_bound_s=0.5):
+        """Scheduling policy: "chunked" (its age bound in seconds), "fifo" or
+        "size_aware" (its share ratio); see dop_serve_set_policy."""
+        param = {"chunked": age_bound_s, "size_aware": share_ratio}.get(policy, 0.0)
+        check(lib().dop_serve_set_policy(self.handle, self.POLICIES[policy], float(param)),
               "dop_serve_set_policy")
 
     def submit(self, prob, h, out, amp=None):

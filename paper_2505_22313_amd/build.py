@@ -13,7 +13,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libdop.so")
 
-SOURCES = ["asm_kernels.hip", "upsample_kernels.hip", "dop_api.cpp", "dop_serve.cpp"]
+SOURCES = ["asm_kernels.hip", "upsample_kernels.hip", "probe_kernels.hip", "dop_api.cpp",
+           "dop_serve.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC",

@@ -1049,9 +1049,15 @@ DOP_KERNEL(Plan<PID>::TA) void k_pass_a_fwd(KParams p) {
     if (tile < 0) continue;
     const int y = tile / RUNS;
     const int xb0 = (tile % RUNS) * RA;
-    // a group of wavelengths shares the tile's heights: each one re-reads
-    // them (from L2) while the previous one is transformed, and writes its
-    // own field
+    // a group of wavelengths shares the tile's heights.  On grids of 2^28
+    // points and more the prefetched values stay in registers for every
+    // member of the group (each forms its field from them and writes its own
+    // workspace field) and the next tile's loads are issued during the last
+    // member's transform, so h crosses the fabric once per group.  Smaller
+    // grids re-read the tile (an L2 hit) for each member: keeping the values
+    // live there made the compiler spill.  (Grids with the factor 67 in x
+    // run one wavelength at a time.)
+    constexpr bool KEEP_H = (size_t)P::MX * P::MY >= (1ull << 28) && n67(AX) == 0;
     for (int q = 0; q < ngroup; ++q) {
       const int tid = loop_tid();
       __syncthreads();
@@ -1079,7 +1085,7 @@ DOP_KERNEL(Plan<PID>::TA) void k_pass_a_fwd(KParams p) {
         }
       }
       if (q + 1 < ngroup) {
-        fetch(tile, tid);
+        if constexpr (!KEEP_H) fetch(tile, tid);
       } else {
         const int nt = seq.tile(k + 1) >= 0 ? seq.tile(k + 1) : seq.tile(k + 2);
         if (nt >= 0) fetch(nt, tid);
@@ -1196,7 +1202,8 @@ DOP_KERNEL(Plan<PID>::TC) void k_pass_c(KParams p) {
   // forward DFT ends in LDS (natural order) and the inverse DFT reads it
   // through a load functor that applies H.
   constexpr bool VIA_LDS = n67(BY) > 0;
-  static_assert((size_t)BY * P::PITCH < (1ull << 31), "tile offsets are 32-bit");
+  static_assert((size_t)BY * P::PITCH * sizeof(float2) <= 0xFFFFFFFFull,
+                "tile byte offsets are 32-bit");
   __shared__ float2 lds[BY * SJ];
   // only BY-point DFTs run here: their twiddles omega_BY^i, i < BY
   __shared__ float2 twc[BY];
@@ -1527,6 +1534,98 @@ DOP_KERNEL(Plan<PID>::TA) void k_pass_a_inv(KParams p) {
         }
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Ceiling probe with pass C's memory access pattern and none of its
+// arithmetic: the same tiles (BY rows x RC columns of the padded-pitch
+// field), the same persistent grid and XCD-aware tile order, the same
+// one-tile-ahead prefetch into the first stage's register layout (which is
+// also the last inverse stage's store layout), the same LDS footprint (so as
+// many blocks share a CU), and each element written back in place times
+// `scale`.  What pass C achieves against this is the share of the pattern's
+// bandwidth its arithmetic leaves.
+// ---------------------------------------------------------------------------
+template <int PID>
+DOP_KERNEL(Plan<PID>::TC) void k_probe_passc(float2 *ws, float scale) {
+  using P = Plan<PID>;
+  constexpr int AY = P::AY, BY = P::BY, RC = P::RC, T = P::TC;
+  constexpr int SJ = RC >= 16 ? RC + 1 : RC;
+  using G = Geo<BY, RC, SJ, 1, T, false>;
+  using FS = FirstStage<G>;
+  static_assert((size_t)BY * P::PITCH * sizeof(float2) <= 0xFFFFFFFFull,
+                "tile byte offsets are 32-bit");
+  constexpr int RUNS = P::MX / RC;
+  constexpr int NT = AY * RUNS;
+  auto tile_base = [&](int pt) {
+    const int tile = xcd_tile(pt, NT);
+    return ws + (size_t)(BY * (tile / RUNS)) * P::PITCH + (tile % RUNS) * RC;
+  };
+  auto off = [&](int j, int b) { return ((unsigned)j * (unsigned)P::PITCH + b) * 8u; };
+  float2 pre[FS::PER][FS::R];
+  auto fetch = [&](int pt, int tid) {
+    const float2 *base = tile_base(pt);
+#pragma unroll
+    for (int i = 0; i < FS::PER; ++i) {
+      const int it = tid + i * T;
+      if (FS::EXACT || it < FS::ITEMS) {
+        int j, b;
+        decode_item<G, FS::R>(it, j, b);
+#pragma unroll
+        for (int t = 0; t < FS::R; ++t) pre[i][t] = *at_byte(base, off(j + t * FS::LR, b));
+      }
+    }
+  };
+  if ((int)blockIdx.x < NT) fetch(blockIdx.x, threadIdx.x);
+  for (int pt = blockIdx.x; pt < NT; pt += gridDim.x) {
+    const int tid = loop_tid();
+    float2 v[FS::PER][FS::R];
+#pragma unroll
+    for (int i = 0; i < FS::PER; ++i)
+#pragma unroll
+      for (int t = 0; t < FS::R; ++t) v[i][t] = pre[i][t];
+    if (pt + (int)gridDim.x < NT) fetch(pt + gridDim.x, tid);
+    float2 *base = tile_base(pt);
+#pragma unroll
+    for (int i = 0; i < FS::PER; ++i) {
+      const int it = tid + i * T;
+      if (FS::EXACT || it < FS::ITEMS) {
+        int j, b;
+        decode_item<G, FS::R>(it, j, b);
+#pragma unroll
+        for (int t = 0; t < FS::R; ++t) *at_byte(base, off(j + t * FS::LR, b)) = cscale(v[i][t], scale);
+      }
+    }
+  }
+}
+
+// LDS bytes of pass C of plan PID (the probe reserves as much, dynamically).
+template <int PID>
+constexpr size_t pass_c_lds_bytes() {
+  using P = Plan<PID>;
+  constexpr int SJ = P::RC >= 16 ? P::RC + 1 : P::RC;
+  constexpr bool VIA_LDS = n67(P::BY) > 0;
+  return sizeof(float2) * (P::BY * SJ + P::BY) + sizeof(double) * (P::BY + (VIA_LDS ? P::RC : 1));
+}
+
+template <int PID>
+static hipError_t launch_probe(float2 *ws, float scale, hipStream_t s) {
+  using P = Plan<PID>;
+  const long long tiles = (long long)P::AY * (P::MX / P::RC);
+  const unsigned grid = (unsigned)(tiles < kMaxBlocks ? tiles : kMaxBlocks);
+  hipLaunchKernelGGL(k_probe_passc<PID>, dim3(grid), dim3(P::TC), pass_c_lds_bytes<PID>(), s, ws,
+                     scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_passc(int plan, float2 *ws, float scale, hipStream_t s) {
+  switch (plan) {
+    case 14: return launch_probe<14>(ws, scale, s);
+    case 15: return launch_probe<15>(ws, scale, s);
+    case 16: return launch_probe<16>(ws, scale, s);
+    case 17: return launch_probe<17>(ws, scale, s);
+    default: return hipErrorInvalidValue;
   }
 }
 

@@ -48,6 +48,7 @@ dop_status fail(dop_status s, const char *fmt, ...) {
 void clear_error() { g_last_error.clear(); }
 
 static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+static bool aligned(const void *p, size_t a) { return reinterpret_cast<uintptr_t>(p) % a == 0; }
 static int upsample_factor(const dop_problem *prob) {
   return prob->upsample <= 1 ? 1 : prob->upsample;
 }
@@ -174,10 +175,10 @@ void fill_common(KParams &kp, const dop_context *ctx, const dop_problem *prob, i
 // Enqueue passes first..last of kp (0 = A ... 4 = A'), bracketed by timing
 // events while profiling is on.
 dop_status launch_range(const dop_context *cctx, const KParams &kp, int first, int last,
-                        hipStream_t stream) {
+                        hipStream_t stream, bool timed = true) {
   dop_context *ctx = const_cast<dop_context *>(cctx);
   std::vector<hipEvent_t> ev;
-  {
+  if (timed) {
     std::lock_guard<std::mutex> lk(ctx->prof_mu);
     if (ctx->prof_on) {
       while ((int)ev.size() < last - first + 2) {
@@ -226,7 +227,14 @@ int psf_group(const dop_problem *prob, const void *saved_u, size_t ws_bytes) {
 
 dop_status enqueue_psf(const dop_context *ctx, const dop_problem *prob, const float *h,
                        const float *amp, float *psf, void *saved_u, void *ws, size_t ws_bytes,
-                       hipStream_t stream) {
+                       hipStream_t stream, bool timed) {
+  return enqueue_psf_range(ctx, prob, 0, prob->n_lambda, h, amp, psf, saved_u, ws, ws_bytes,
+                           stream, timed);
+}
+
+dop_status enqueue_psf_range(const dop_context *ctx, const dop_problem *prob, int kbeg, int kend,
+                             const float *h, const float *amp, float *psf, void *saved_u, void *ws,
+                             size_t ws_bytes, hipStream_t stream, bool timed) {
   const size_t nn = (size_t)doe_rows(prob) * prob->n;
   const int g = psf_group(prob, saved_u, ws_bytes);
   auto setup = [&](KParams &kp, int k, void *field) {
@@ -239,14 +247,14 @@ dop_status enqueue_psf(const dop_context *ctx, const dop_problem *prob, const fl
     kp.amp = amp;
     kp.psf = psf;
   };
-  for (int k0 = 0; k0 < prob->n_lambda;) {
-    const int gk = prob->n_lambda - k0 < g ? prob->n_lambda - k0 : g;
+  for (int k0 = kbeg; k0 < kend;) {
+    const int gk = kend - k0 < g ? kend - k0 : g;
     if (gk == 1) {
       KParams kp;
       setup(kp, k0, ws);
       kp.first = (k0 == 0);
       kp.saved_out = saved_u ? static_cast<float2 *>(saved_u) + (size_t)k0 * nn : nullptr;
-      const dop_status s = launch(ctx, kp, stream);
+      const dop_status s = launch_range(ctx, kp, 0, kNumPasses - 1, stream, timed);
       if (s != DOP_OK) return s;
     } else {
       // a group: pass A forms the gk fields from one read of the heights,
@@ -263,15 +271,15 @@ dop_status enqueue_psf(const dop_context *ctx, const dop_problem *prob, const fl
         g0.phase_turns_g[q] = kq.phase_turns;
         g0.wk_m4_g[q] = kq.wk_m4;
       }
-      dop_status s = launch_range(ctx, g0, 0, 0, stream);
+      dop_status s = launch_range(ctx, g0, 0, 0, stream, timed);
       if (s != DOP_OK) return s;
       for (int q = 0; q < gk; ++q) {
         KParams kq;
         setup(kq, k0 + q, static_cast<float2 *>(ws) + (size_t)q * g0.field_elems);
-        s = launch_range(ctx, kq, 1, 3, stream);
+        s = launch_range(ctx, kq, 1, 3, stream, timed);
         if (s != DOP_OK) return s;
       }
-      s = launch_range(ctx, g0, kNumPasses - 1, kNumPasses - 1, stream);
+      s = launch_range(ctx, g0, kNumPasses - 1, kNumPasses - 1, stream, timed);
       if (s != DOP_OK) return s;
     }
     k0 += gk;
@@ -409,6 +417,39 @@ dop_status dop_profile_read(dop_context *ctx, dop_pass_profile *out, int max, in
   return DOP_OK;
 }
 
+dop_status dop_probe_bandwidth(dop_context *ctx, int kind, void *buf, size_t bytes, int m,
+                               size_t *moved, void *stream) {
+  clear_error();
+  if (!ctx) return fail(DOP_ERR_INVALID_ARG, "context is NULL");
+  if (!buf || !moved) return fail(DOP_ERR_INVALID_ARG, "buf / moved must not be NULL");
+  if (!aligned(buf, 256)) return fail(DOP_ERR_INVALID_ARG, "buf must be 256-byte aligned");
+  if (bytes < 64 || bytes % 64 != 0)
+    return fail(DOP_ERR_INVALID_ARG, "bytes must be a positive multiple of 64 (got %zu)", bytes);
+  if (kind < DOP_PROBE_READ || kind > DOP_PROBE_PASSC)
+    return fail(DOP_ERR_INVALID_ARG, "unknown probe kind %d", kind);
+  size_t mv = 0;
+  if (kind == DOP_PROBE_PASSC) {
+    if (m < 16384 || m > DOP_MAX_M || !is_pow2(m))
+      return fail(DOP_ERR_UNSUPPORTED, "the pass-C probe needs m = 16384 .. %d, a power of two "
+                  "(got %d)", DOP_MAX_M, m);
+    const size_t need = (size_t)m * ((size_t)m + kRowPad) * sizeof(float2);
+    if (bytes < need)
+      return fail(DOP_ERR_WORKSPACE, "buf has %zu bytes, the %d^2 field needs %zu", bytes, m, need);
+    mv = 2 * sizeof(float2) * (size_t)m * (size_t)m;
+  } else {
+    mv = kind == DOP_PROBE_INPLACE ? 2 * bytes : bytes;
+  }
+  dop_status s = check_ctx_device(ctx);
+  if (s != DOP_OK) return s;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const hipError_t e = kind == DOP_PROBE_PASSC
+                           ? launch_probe_passc(ilog2i(m), static_cast<float2 *>(buf), 1.0f, st)
+                           : launch_probe_stream(kind, buf, bytes / 16, 1.0f, st);
+  if (e != hipSuccess) return fail(DOP_ERR_DEVICE, "probe launch failed: %s", hipGetErrorString(e));
+  *moved = mv;
+  return DOP_OK;
+}
+
 dop_status dop_workspace_size(const dop_context *ctx, const dop_problem *prob, int op,
                               size_t *bytes) {
   clear_error();
@@ -432,7 +473,6 @@ static dop_status check_ws(const dop_problem *prob, int op, void *ws, size_t ws_
   return DOP_OK;
 }
 
-static bool aligned(const void *p, size_t a) { return reinterpret_cast<uintptr_t>(p) % a == 0; }
 
 dop_status dop_propagate(dop_context *ctx, const dop_problem *prob, int k, const void *u_in,
                          void *u_out, void *ws, size_t ws_bytes, void *stream) {
@@ -461,11 +501,11 @@ dop_status dop_propagate(dop_context *ctx, const dop_problem *prob, int k, const
   return launch(ctx, kp, static_cast<hipStream_t>(stream));
 }
 
-dop_status dop_psf(dop_context *ctx, const dop_problem *prob, const float *h, const float *amp,
-                   float *psf, void *saved_u, void *ws, size_t ws_bytes, void *stream) {
-  clear_error();
+// Checks of dop_psf's arguments other than the workspace.
+static dop_status check_psf_args(const dop_context *ctx, const dop_problem *prob, const float *h,
+                                 const float *amp, const float *psf, const void *saved_u) {
   if (!ctx) return fail(DOP_ERR_INVALID_ARG, "context is NULL");
-  dop_status s = validate_problem(prob);
+  const dop_status s = validate_problem(prob);
   if (s != DOP_OK) return s;
   if (!h || !psf) return fail(DOP_ERR_INVALID_ARG, "h / psf must not be NULL");
   if (!aligned(h, 4) || !aligned(psf, 4) || (amp && !aligned(amp, 4)))
@@ -474,6 +514,14 @@ dop_status dop_psf(dop_context *ctx, const dop_problem *prob, const float *h, co
     return fail(DOP_ERR_UNSUPPORTED, "saved_u requires DOP_OUT_CROP");
   if (saved_u && !aligned(saved_u, 8))
     return fail(DOP_ERR_INVALID_ARG, "saved_u must be 8-byte aligned");
+  return DOP_OK;
+}
+
+dop_status dop_psf(dop_context *ctx, const dop_problem *prob, const float *h, const float *amp,
+                   float *psf, void *saved_u, void *ws, size_t ws_bytes, void *stream) {
+  clear_error();
+  dop_status s = check_psf_args(ctx, prob, h, amp, psf, saved_u);
+  if (s != DOP_OK) return s;
   if ((s = check_ws(prob, DOP_OP_PSF, ws, ws_bytes)) != DOP_OK) return s;
   if ((s = check_ctx_device(ctx)) != DOP_OK) return s;
   return enqueue_psf(ctx, prob, h, amp, psf, saved_u, ws, ws_bytes,

@@ -27,10 +27,19 @@ size_t workspace_bytes(const dop_problem *prob);
 
 // Enqueue the whole PSF of `prob` (all wavelengths) on `stream`.  A workspace
 // of g >= 2 fields (ws_bytes) lets wavelengths run in groups of up to g (see
-// psf_group).
+// psf_group).  With `timed` false the passes are never bracketed by timing
+// events, even while profiling is on (so the call creates no events).
 dop_status enqueue_psf(const dop_context *ctx, const dop_problem *prob, const float *h,
                        const float *amp, float *psf, void *saved_u, void *ws, size_t ws_bytes,
-                       hipStream_t stream);
+                       hipStream_t stream, bool timed = true);
+
+// The same for wavelengths kbeg..kend-1 only (0 <= kbeg < kend <= K): their
+// terms are added to the PSF (wavelength 0 overwrites it), in the order and
+// rounding of the whole call, so consecutive ranges that cover 0..K-1, run in
+// order, give the whole call's PSF bitwise.
+dop_status enqueue_psf_range(const dop_context *ctx, const dop_problem *prob, int kbeg, int kend,
+                             const float *h, const float *amp, float *psf, void *saved_u, void *ws,
+                             size_t ws_bytes, hipStream_t stream, bool timed = true);
 
 // Wavelengths per group that dop_psf uses for `prob` with a workspace of
 // ws_bytes: as many whole fields as fit, at most the plan's limit and the

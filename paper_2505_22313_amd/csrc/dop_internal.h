@@ -117,6 +117,13 @@ struct PlanInfo {
 };
 bool plan_info(int plan, PlanInfo *out);
 
+// Bandwidth probes (dop_probe_bandwidth): pass C's access pattern without its
+// arithmetic on the power-of-two grid of plan id `plan` (14..17), and plain
+// 16-byte stream kernels over n16 16-byte vectors.  Arguments already
+// validated.
+hipError_t launch_probe_passc(int plan, float2 *ws, float scale, hipStream_t stream);
+hipError_t launch_probe_stream(int kind, void *buf, size_t n16, float scale, hipStream_t stream);
+
 // Super-resolved front end: fine = Wy coarse Wx^T and its adjoint for a
 // coarse design of ncy rows and ncx columns (kind 0: nearest, 1: Lanczos-3;
 // see dop_upsample).  Arguments already validated.

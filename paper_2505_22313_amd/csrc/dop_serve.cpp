@@ -1,13 +1,32 @@
 // Continuous-batching PSF server.
 //
-// Requests are queued FIFO.  A scheduler thread admits the head of the queue
-// as soon as a slot is free and its workspace fits in the caller's device
-// arena (first-fit sub-allocator, no hipMalloc per request), enqueues the
-// request's passes on that slot's stream and records an event.  Completed
-// events release the slot and the arena range, which admits the next
-// requests while others are still running, so the passes of several requests
-// overlap on the device.  Results do not depend on what runs beside them:
-// every kernel is deterministic and each request has its own workspace.
+// Requests are queued in submission order.  A scheduler thread admits them
+// as request slots and arena memory free up (each admitted request holds its
+// own workspace, sub-allocated first-fit from the caller's device arena: no
+// hipMalloc per request) and feeds their work to the GPU under one of three
+// policies:
+//
+//  - DOP_SERVE_CHUNKED (default): a request's wavelengths run in chunks of
+//    one wavelength group (up to four wavelengths that share one read of the
+//    heights and one read-modify-write of the PSF).  Chunks of all admitted
+//    requests go through one in-order stream, at most kDepth enqueued at a
+//    time.  Each time a chunk completes, the next one is taken from the
+//    admitted request with the least work left (shortest remaining
+//    processing time), unless requests have waited longer than the age bound:
+//    then the oldest of those goes first.  A request that arrives while a
+//    large one runs waits for at most kDepth chunks instead of the whole
+//    large request, and the large one is never slowed by sharing the GPU: it
+//    only pauses.  Admission takes the head of the queue first; a request
+//    behind a head that does not fit yet may go ahead of it unless the head
+//    has passed the age bound.
+//  - DOP_SERVE_FIFO and DOP_SERVE_SIZE_AWARE: a request's whole PSF is
+//    enqueued at admission on the stream of its slot, so admitted requests
+//    run side by side (processor sharing); admission is strictly in order.
+//
+// Results do not depend on the schedule: every kernel is deterministic, each
+// request has its own workspace and output, its chunks run in wavelength
+// order on one stream, and a chunk adds its wavelengths to the PSF in the
+// order and rounding of one dop_psf call.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -16,6 +35,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <list>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -34,6 +54,15 @@ static double now_s() {
   return std::chrono::duration<double>(Clock::now().time_since_epoch()).count();
 }
 
+// Chunks enqueued ahead on the chunked policy's stream: one running and one
+// waiting behind it, so the GPU does not idle while the scheduler picks.
+constexpr int kDepth = 2;
+// Queue entries the chunked policy's admission looks at past a head that
+// does not fit yet.
+constexpr int kAdmitLookahead = 32;
+// Default age bound of the chunked policy (seconds).
+constexpr double kDefaultAgeBound = 0.5;
+
 struct Request {
   uint64_t ticket = 0;
   dop_problem prob{};
@@ -41,11 +70,17 @@ struct Request {
   std::vector<float> weight;
   const float *h = nullptr, *amp = nullptr;
   float *psf = nullptr;
-  size_t need = 0;
+  size_t field = 0;      // bytes of one workspace field
+  size_t need = 0;       // workspace bytes held while admitted
+  int group = 1;         // wavelengths per chunk (fields in the workspace)
+  bool chunked = false;  // admitted under DOP_SERVE_CHUNKED
   double t_submit = 0, t_done = 0;
   dop_status status = DOP_NOT_READY;
-  int slot = -1;
+  int slot = -1;         // whole-request policies: the slot (and stream) it runs on
   size_t off = 0;
+  int k_next = 0;        // first wavelength not yet enqueued
+  int inflight = 0;      // chunks enqueued and not yet complete
+  dop_status err = DOP_OK;  // first chunk error (no further chunks after one)
 };
 
 // First-fit sub-allocator over [0, size) with coalescing free ranges.
@@ -53,8 +88,9 @@ class Arena {
  public:
   explicit Arena(size_t size) : size_(size) { free_[0] = size; }
   static constexpr size_t kAlign = 256;
+  static size_t round(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
   bool alloc(size_t bytes, size_t *off) {
-    bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+    bytes = round(bytes);
     for (auto it = free_.begin(); it != free_.end(); ++it) {
       if (it->second >= bytes) {
         *off = it->first;
@@ -70,7 +106,7 @@ class Arena {
     return false;
   }
   void release(size_t off, size_t bytes) {
-    bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+    bytes = round(bytes);
     used_ -= bytes;
     auto it = free_.emplace(off, bytes).first;
     auto nx = std::next(it);
@@ -95,27 +131,50 @@ class Arena {
   std::map<size_t, size_t> free_;
 };
 
-// Executes admitted requests.  start() enqueues without blocking; done()
-// polls without blocking and, once true, result() gives the status.
+// Executes chunks (wavelengths [k0, k1) of a request) on lanes (in-order
+// streams).  start() enqueues without blocking and names the chunk by a
+// token; done() polls without blocking; release() returns the token.
 class Executor {
  public:
   virtual ~Executor() = default;
   virtual void thread_init() {}
-  virtual dop_status start(int slot, Request &r, void *ws, size_t ws_bytes) = 0;
-  virtual bool done(int slot, dop_status *st) = 0;
+  virtual dop_status start(int lane, Request &r, int k0, int k1, void *ws, size_t ws_bytes,
+                           int *token) = 0;
+  virtual bool done(int token, dop_status *st) = 0;
+  virtual void release(int token) = 0;
+};
+
+// Tokens 0..n-1 handed out and returned.
+class TokenPool {
+ public:
+  explicit TokenPool(int n) {
+    for (int i = n - 1; i >= 0; --i) free_.push_back(i);
+  }
+  bool take(int *t) {
+    if (free_.empty()) return false;
+    *t = free_.back();
+    free_.pop_back();
+    return true;
+  }
+  void give(int t) { free_.push_back(t); }
+
+ private:
+  std::vector<int> free_;
 };
 
 class GpuExecutor : public Executor {
  public:
-  GpuExecutor(dop_context *ctx, int slots) : ctx_(ctx), streams_(slots), events_(slots) {}
+  // lanes streams; at most `tokens` chunks in flight (one completion event each)
+  GpuExecutor(dop_context *ctx, int lanes, int tokens)
+      : ctx_(ctx), streams_(lanes), events_(tokens), pool_(tokens) {}
   dop_status init() {
     (void)hipSetDevice(context_device(ctx_));
-    for (size_t i = 0; i < streams_.size(); ++i) {
-      if (hipStreamCreateWithFlags(&streams_[i], hipStreamNonBlocking) != hipSuccess)
+    for (auto &s : streams_)
+      if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
         return fail(DOP_ERR_DEVICE, "hipStreamCreate failed");
-      if (hipEventCreateWithFlags(&events_[i], hipEventDisableTiming) != hipSuccess)
+    for (auto &e : events_)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
         return fail(DOP_ERR_DEVICE, "hipEventCreate failed");
-    }
     return DOP_OK;
   }
   ~GpuExecutor() override {
@@ -127,46 +186,65 @@ class GpuExecutor : public Executor {
       if (s) (void)hipStreamDestroy(s);
   }
   void thread_init() override { (void)hipSetDevice(context_device(ctx_)); }
-  dop_status start(int slot, Request &r, void *ws, size_t ws_bytes) override {
-    dop_status s =
-        enqueue_psf(ctx_, &r.prob, r.h, r.amp, r.psf, nullptr, ws, ws_bytes, streams_[slot]);
-    if (s != DOP_OK) return s;
-    if (hipEventRecord(events_[slot], streams_[slot]) != hipSuccess)
-      return fail(DOP_ERR_DEVICE, "hipEventRecord failed");
+  dop_status start(int lane, Request &r, int k0, int k1, void *ws, size_t ws_bytes,
+                   int *token) override {
+    int t = 0;
+    if (!pool_.take(&t)) return fail(DOP_ERR_DEVICE, "no completion event free");
+    dop_status s = enqueue_psf_range(ctx_, &r.prob, k0, k1, r.h, r.amp, r.psf, nullptr, ws,
+                                     ws_bytes, streams_[lane]);
+    if (s == DOP_OK && hipEventRecord(events_[t], streams_[lane]) != hipSuccess)
+      s = fail(DOP_ERR_DEVICE, "hipEventRecord failed");
+    if (s != DOP_OK) {
+      // work enqueued before the failure still runs: wait for it before the
+      // workspace can be handed to another request
+      (void)hipStreamSynchronize(streams_[lane]);
+      pool_.give(t);
+      return s;
+    }
+    *token = t;
     return DOP_OK;
   }
-  bool done(int slot, dop_status *st) override {
-    const hipError_t e = hipEventQuery(events_[slot]);
+  bool done(int token, dop_status *st) override {
+    const hipError_t e = hipEventQuery(events_[token]);
     if (e == hipErrorNotReady) return false;
     *st = (e == hipSuccess) ? DOP_OK : DOP_ERR_DEVICE;
     return true;
   }
+  void release(int token) override { pool_.give(token); }
 
  private:
   dop_context *ctx_;
   std::vector<hipStream_t> streams_;
   std::vector<hipEvent_t> events_;
+  TokenPool pool_;
 };
 
-// Host-only stand-in: a request occupies its slot for a wall time
-// proportional to K * M^2.
+// Host-only stand-in: each lane is an in-order queue whose chunks occupy it
+// for service_us_per_mpix * (chunk wavelengths * M^2 / 1e6) microseconds of
+// wall time; nothing is written.
 class MockExecutor : public Executor {
  public:
-  MockExecutor(int slots, double us_per_mpix) : end_(slots, 0.0), us_per_mpix_(us_per_mpix) {}
-  dop_status start(int slot, Request &r, void *, size_t) override {
-    const double mpix =
-        (double)r.prob.n_lambda * grid_cols(&r.prob) * (double)grid_rows(&r.prob) / 1e6;
-    end_[slot] = now_s() + us_per_mpix_ * mpix * 1e-6;
+  MockExecutor(int lanes, int tokens, double us_per_mpix)
+      : lane_end_(lanes, 0.0), tok_end_(tokens, 0.0), pool_(tokens), us_per_mpix_(us_per_mpix) {}
+  dop_status start(int lane, Request &r, int k0, int k1, void *, size_t, int *token) override {
+    int t = 0;
+    if (!pool_.take(&t)) return fail(DOP_ERR_DEVICE, "no completion token free");
+    const double mpix = (double)(k1 - k0) * grid_cols(&r.prob) * (double)grid_rows(&r.prob) / 1e6;
+    lane_end_[lane] = std::max(now_s(), lane_end_[lane]) + us_per_mpix_ * mpix * 1e-6;
+    tok_end_[t] = lane_end_[lane];
+    *token = t;
     return DOP_OK;
   }
-  bool done(int slot, dop_status *st) override {
-    if (now_s() < end_[slot]) return false;
+  bool done(int token, dop_status *st) override {
+    if (now_s() < tok_end_[token]) return false;
     *st = DOP_OK;
     return true;
   }
+  void release(int token) override { pool_.give(token); }
 
  private:
-  std::vector<double> end_;
+  std::vector<double> lane_end_, tok_end_;
+  TokenPool pool_;
   double us_per_mpix_;
 };
 
@@ -175,6 +253,13 @@ class MockExecutor : public Executor {
 using namespace dop;
 
 struct dop_server {
+  struct Chunk {
+    int token;
+    Request *r;
+    int k_end;
+    int lane;
+  };
+
   std::unique_ptr<Executor> ex;
   char *arena_base = nullptr;
   Arena arena;
@@ -183,13 +268,15 @@ struct dop_server {
   std::condition_variable cv_work, cv_done;
   std::deque<Request *> queue;
   std::unordered_map<uint64_t, std::unique_ptr<Request>> all;
-  std::vector<Request *> slots;
+  std::vector<Request *> slots;  // admitted requests by slot (whole-request lanes)
+  std::list<Chunk> chunks;       // enqueued, not yet complete, in enqueue order
   std::vector<double> latencies_ms;
   uint64_t next_ticket = 1;
   uint64_t submitted = 0, completed = 0, failed = 0;
   bool stopping = false;
-  int policy = DOP_SERVE_FIFO;
-  double share_ratio = 0.25;
+  int policy = DOP_SERVE_CHUNKED;
+  double share_ratio = 0.25;            // DOP_SERVE_SIZE_AWARE
+  double age_bound = kDefaultAgeBound;  // DOP_SERVE_CHUNKED, seconds
   std::thread sched;
 
   dop_server(char *base, size_t bytes, int n) : arena_base(base), arena(bytes), max_slots(n),
@@ -198,6 +285,10 @@ struct dop_server {
   // padded pixels x wavelengths: the request's share of GPU time
   static double work(const Request &r) {
     return (double)r.prob.n_lambda * (double)grid_cols(&r.prob) * (double)grid_rows(&r.prob);
+  }
+  static double work_left(const Request &r) {
+    return (double)(r.prob.n_lambda - r.k_next) * (double)grid_cols(&r.prob) *
+           (double)grid_rows(&r.prob);
   }
 
   void finish(Request *r, dop_status st) {
@@ -208,56 +299,171 @@ struct dop_server {
     if (st != DOP_OK) ++failed;
   }
 
+  int running() const {
+    int n = 0;
+    for (Request *r : slots)
+      if (r) ++n;
+    return n;
+  }
+
+  int free_slot() const {
+    for (int s = 0; s < max_slots; ++s)
+      if (!slots[s]) return s;
+    return -1;
+  }
+
+  // Finished or failed with nothing in flight: release its slot and memory.
+  void retire_if_done(Request *r) {
+    if (r->inflight > 0) return;
+    if (r->err == DOP_OK && r->k_next < r->prob.n_lambda) return;
+    arena.release(r->off, r->need);
+    slots[r->slot] = nullptr;
+    finish(r, r->err);
+  }
+
+  // Enqueue wavelengths [k_next, k1) of r on `lane`.
+  void start_chunk(Request *r, int k1, int lane) {
+    int tok = 0;
+    const dop_status st = ex->start(lane, *r, r->k_next, k1, arena_base + r->off, r->need, &tok);
+    if (st != DOP_OK) {
+      r->err = st;
+      retire_if_done(r);
+      return;
+    }
+    r->k_next = k1;
+    ++r->inflight;
+    chunks.push_back({tok, r, k1, lane});
+  }
+
+  // Reserve a slot and workspace for r and admit it under the current policy.
+  bool try_admit(Request *r) {
+    const int s = free_slot();
+    if (s < 0) return false;
+    const bool ch = policy == DOP_SERVE_CHUNKED;
+    // whole-request policies run one wavelength at a time in one field; the
+    // chunked policy gives a request up to a wavelength group of fields, at
+    // most half the arena, or one field if that is all that fits now
+    int g = 1;
+    if (ch) {
+      g = psf_group(&r->prob, nullptr, (size_t)-1);
+      while (g > 1 && Arena::round((size_t)g * r->field) > arena.size() / 2) --g;
+    }
+    size_t off = 0;
+    while (!arena.alloc((size_t)g * r->field, &off)) {
+      if (g == 1) return false;
+      g = 1;
+    }
+    r->group = g;
+    r->need = (size_t)g * r->field;
+    r->off = off;
+    r->slot = s;
+    r->chunked = ch;
+    slots[s] = r;
+    if (!ch) start_chunk(r, r->prob.n_lambda, s);
+    return true;
+  }
+
+  void admit(double now) {
+    while (!stopping && !queue.empty() && free_slot() >= 0) {
+      Request *head = queue.front();
+      if (policy == DOP_SERVE_SIZE_AWARE && running() > 0) {
+        // the head shares the GPU only if it is small next to what runs
+        double wmax = 0.0;
+        for (Request *q : slots)
+          if (q) wmax = std::max(wmax, work(*q));
+        if (work(*head) > share_ratio * wmax) return;
+      }
+      if (try_admit(head)) {
+        queue.pop_front();
+        continue;
+      }
+      // the head does not fit yet: in order for the whole-request policies,
+      // and under the chunked policy while the head has passed the age bound
+      if (policy != DOP_SERVE_CHUNKED || now - head->t_submit > age_bound) return;
+      bool admitted = false;
+      int seen = 0;
+      for (auto it = std::next(queue.begin()); it != queue.end() && seen < kAdmitLookahead;
+           ++it, ++seen) {
+        if (try_admit(*it)) {
+          queue.erase(it);
+          admitted = true;
+          break;
+        }
+      }
+      if (!admitted) return;
+    }
+  }
+
+  // The chunked request whose next chunk goes next, or NULL.
+  Request *pick(double now) const {
+    Request *best = nullptr;
+    bool best_aged = false;
+    for (Request *r : slots) {
+      if (!r || !r->chunked || r->err != DOP_OK || r->k_next >= r->prob.n_lambda) continue;
+      const bool aged = now - r->t_submit > age_bound;
+      if (!best) {
+        best = r;
+        best_aged = aged;
+        continue;
+      }
+      if (aged != best_aged) {
+        if (aged) {
+          best = r;
+          best_aged = true;
+        }
+        continue;
+      }
+      const bool better = aged ? r->ticket < best->ticket
+                               : (work_left(*r) < work_left(*best) ||
+                                  (work_left(*r) == work_left(*best) && r->ticket < best->ticket));
+      if (better) best = r;
+    }
+    return best;
+  }
+
+  void feed(double now) {
+    int on_lane0 = 0;
+    for (const Chunk &c : chunks)
+      if (c.r->chunked) ++on_lane0;
+    while (on_lane0 < kDepth) {
+      Request *r = pick(now);
+      if (!r) return;
+      const int k1 = std::min(r->prob.n_lambda, r->k_next + r->group);
+      const size_t before = chunks.size();
+      start_chunk(r, k1, 0);
+      if (chunks.size() > before) ++on_lane0;
+    }
+  }
+
   void loop() {
     ex->thread_init();
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
       bool any_done = false;
-      int running = 0;
-      for (int s = 0; s < max_slots; ++s) {
-        Request *r = slots[s];
-        if (!r) continue;
+      for (auto it = chunks.begin(); it != chunks.end();) {
         dop_status st;
-        if (ex->done(s, &st)) {
-          arena.release(r->off, r->need);
-          slots[s] = nullptr;
-          finish(r, st);
-          any_done = true;
-        } else {
-          ++running;
+        if (!ex->done(it->token, &st)) {
+          ++it;
+          continue;
         }
+        Request *r = it->r;
+        ex->release(it->token);
+        --r->inflight;
+        if (st != DOP_OK && r->err == DOP_OK) r->err = st;
+        it = chunks.erase(it);
+        const uint64_t before = completed;
+        retire_if_done(r);
+        any_done = any_done || completed != before;
       }
-      while (!stopping && !queue.empty()) {
-        Request *r = queue.front();
-        int free_slot = -1;
-        for (int s = 0; s < max_slots; ++s)
-          if (!slots[s]) { free_slot = s; break; }
-        if (free_slot < 0) break;
-        if (policy == DOP_SERVE_SIZE_AWARE && running > 0) {
-          // the head shares the GPU only if it is small next to what runs
-          double wmax = 0.0;
-          for (Request *q : slots)
-            if (q) wmax = std::max(wmax, work(*q));
-          if (work(*r) > share_ratio * wmax) break;
-        }
-        size_t off = 0;
-        if (!arena.alloc(r->need, &off)) break;  // FIFO: the head waits for memory
-        queue.pop_front();
-        r->slot = free_slot;
-        r->off = off;
-        const dop_status st = ex->start(free_slot, *r, arena_base + off, r->need);
-        if (st != DOP_OK) {
-          arena.release(off, r->need);
-          finish(r, st);
-          any_done = true;
-        } else {
-          slots[free_slot] = r;
-          ++running;
-        }
-      }
+      const double now = now_s();
+      const uint64_t before = completed;
+      admit(now);
+      feed(now);
+      any_done = any_done || completed != before;
       if (any_done) cv_done.notify_all();
-      if (stopping && running == 0) break;
-      if (running == 0 && queue.empty()) {
+      const bool idle = chunks.empty() && running() == 0;
+      if (stopping && idle) break;
+      if (idle && queue.empty()) {
         cv_work.wait(lk);
       } else {
         lk.unlock();
@@ -289,7 +495,7 @@ dop_status dop_serve_create(dop_context *ctx, void *arena, size_t arena_bytes, i
   if (reinterpret_cast<uintptr_t>(arena) % Arena::kAlign != 0)
     return fail(DOP_ERR_INVALID_ARG, "arena must be %zu-byte aligned", Arena::kAlign);
   if (max_slots < 1 || max_slots > 64) return fail(DOP_ERR_INVALID_ARG, "max_slots must be 1..64");
-  auto ex = std::make_unique<GpuExecutor>(ctx, max_slots);
+  auto ex = std::make_unique<GpuExecutor>(ctx, max_slots, max_slots + kDepth);
   const dop_status s = ex->init();
   if (s != DOP_OK) return s;
   return make_server(std::move(ex), arena, arena_bytes, max_slots, out);
@@ -303,8 +509,9 @@ dop_status dop_serve_create_mock(void *arena, size_t arena_bytes, int max_slots,
   if (!arena || arena_bytes == 0) return fail(DOP_ERR_INVALID_ARG, "arena is empty");
   if (max_slots < 1 || max_slots > 64) return fail(DOP_ERR_INVALID_ARG, "max_slots must be 1..64");
   if (!(service_us_per_mpix >= 0.0)) return fail(DOP_ERR_INVALID_ARG, "service time must be >= 0");
-  return make_server(std::make_unique<MockExecutor>(max_slots, service_us_per_mpix), arena,
-                     arena_bytes, max_slots, out);
+  return make_server(std::make_unique<MockExecutor>(max_slots, max_slots + kDepth,
+                                                    service_us_per_mpix),
+                     arena, arena_bytes, max_slots, out);
 }
 
 dop_status dop_serve_submit(dop_server *srv, const dop_problem *prob, const float *h,
@@ -331,12 +538,12 @@ dop_status dop_serve_submit(dop_server *srv, const dop_problem *prob, const floa
   r->h = h;
   r->amp = amp;
   r->psf = psf;
-  r->need = workspace_bytes(prob);
+  r->field = workspace_bytes(prob);
   {
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->stopping) return fail(DOP_ERR_SHUTDOWN, "server is shutting down");
-    if ((r->need + Arena::kAlign - 1) / Arena::kAlign * Arena::kAlign > srv->arena.size())
-      return fail(DOP_ERR_BUDGET, "request needs %zu bytes, arena holds %zu", r->need,
+    if (Arena::round(r->field) > srv->arena.size())
+      return fail(DOP_ERR_BUDGET, "request needs %zu bytes, arena holds %zu", r->field,
                   srv->arena.size());
     r->ticket = srv->next_ticket++;
     r->t_submit = now_s();
@@ -349,17 +556,18 @@ dop_status dop_serve_submit(dop_server *srv, const dop_problem *prob, const floa
   return DOP_OK;
 }
 
-dop_status dop_serve_set_policy(dop_server *srv, int policy, double share_ratio) {
+dop_status dop_serve_set_policy(dop_server *srv, int policy, double param) {
   clear_error();
   if (!srv) return fail(DOP_ERR_INVALID_ARG, "server is NULL");
-  if (policy != DOP_SERVE_FIFO && policy != DOP_SERVE_SIZE_AWARE)
+  if (policy != DOP_SERVE_FIFO && policy != DOP_SERVE_SIZE_AWARE && policy != DOP_SERVE_CHUNKED)
     return fail(DOP_ERR_INVALID_ARG, "unknown policy %d", policy);
-  if (!(share_ratio >= 0.0) || !std::isfinite(share_ratio))
-    return fail(DOP_ERR_INVALID_ARG, "share_ratio must be finite and >= 0");
+  if (!(param >= 0.0) || !std::isfinite(param))
+    return fail(DOP_ERR_INVALID_ARG, "the policy parameter must be finite and >= 0");
   {
     std::lock_guard<std::mutex> lk(srv->mu);
     srv->policy = policy;
-    srv->share_ratio = share_ratio;
+    if (policy == DOP_SERVE_SIZE_AWARE) srv->share_ratio = param;
+    if (policy == DOP_SERVE_CHUNKED) srv->age_bound = param;
   }
   srv->cv_work.notify_one();
   return DOP_OK;
@@ -413,10 +621,7 @@ dop_status dop_serve_stats_get(dop_server *srv, dop_serve_stats *out) {
   st.completed = srv->completed;
   st.failed = srv->failed;
   st.queued = (uint32_t)srv->queue.size();
-  uint32_t running = 0;
-  for (auto r : srv->slots)
-    if (r) ++running;
-  st.running = running;
+  st.running = (uint32_t)srv->running();
   st.arena_bytes = srv->arena.size();
   st.arena_peak = srv->arena.peak();
   if (!srv->latencies_ms.empty()) {

@@ -48,8 +48,22 @@ size_t workspace_bytes(const dop_problem *p) {
 }
 
 dop_status enqueue_psf(const dop_context *, const dop_problem *, const float *, const float *,
-                       float *, void *, void *, size_t, hipStream_t) {
+                       float *, void *, void *, size_t, hipStream_t, bool) {
   return fail(DOP_ERR_DEVICE, "no GPU in the host sanitizer build");
+}
+
+dop_status enqueue_psf_range(const dop_context *, const dop_problem *, int, int, const float *,
+                             const float *, float *, void *, void *, size_t, hipStream_t, bool) {
+  return fail(DOP_ERR_DEVICE, "no GPU in the host sanitizer build");
+}
+
+// Wavelength groups as the library forms them: up to four, as many as fit.
+int psf_group(const dop_problem *p, const void *saved_u, size_t ws_bytes) {
+  if (saved_u) return 1;
+  const size_t fit = ws_bytes / workspace_bytes(p);
+  int g = p->n_lambda < 4 ? p->n_lambda : 4;
+  if (fit < (size_t)g) g = (int)fit;
+  return g < 1 ? 1 : g;
 }
 
 int context_device(const dop_context *) { return 0; }

@@ -1,12 +1,14 @@
 // Concurrency stress of the serving engine's scheduler through its C ABI,
-// with the host-side mock executor (no GPU).  Built and run under GCC's
-// thread sanitizer and under its address + undefined-behaviour sanitizers
+// with the host-side mock executor (no GPU).  Built and run under the
+// thread sanitizer and under the address + undefined-behaviour sanitizers
 // by tests/test_serve_sanitizers_cpu.py; any report fails the run.
 //
 // Scenarios:
 //  1. four submitter threads, each with its own waiter thread (poll, wait,
-//     latency), a statistics reader and a policy switcher, all at once,
-//     against a 4-slot server whose arena admits only a few requests;
+//     latency), a statistics reader and a policy switcher cycling through
+//     the chunked, size-aware and FIFO policies, all at once, against a
+//     4-slot server whose arena admits only a few requests (requests of
+//     several policies are admitted and run side by side);
 //  2. requests that can never fit the arena (budget error) and invalid
 //     arguments, from several threads;
 //  3. shutdown with requests still queued and running.
@@ -104,8 +106,9 @@ static void scenario_concurrent() {
   th.emplace_back([&] {  // policy switcher
     int i = 0;
     while (!stop.load()) {
-      const int pol = (i++ & 1) ? DOP_SERVE_SIZE_AWARE : DOP_SERVE_FIFO;
-      CHECK(dop_serve_set_policy(srv, pol, 0.25) == DOP_OK);
+      const int pols[3] = {DOP_SERVE_CHUNKED, DOP_SERVE_SIZE_AWARE, DOP_SERVE_FIFO};
+      const int pol = pols[i++ % 3];
+      CHECK(dop_serve_set_policy(srv, pol, pol == DOP_SERVE_CHUNKED ? 0.001 : 0.25) == DOP_OK);
       std::this_thread::sleep_for(std::chrono::microseconds(200));
     }
   });

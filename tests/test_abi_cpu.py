@@ -259,10 +259,9 @@ def test_serve_slots_limit_concurrency():
 
 
 def test_serve_fifo_head_of_line():
-    """A request that does not fit yet holds back the ones behind it, so
+    """FIFO: a request that does not fit yet holds back the ones behind it, so
     admission order is submission order."""
-    unit = ws(1024)                    # one 1024^2 workspace
-    srv = api.Server(ws(2048), max_slots=4, mock_us_per_mpix=3000.0)
+    srv = api.Server(ws(2048), max_slots=4, mock_us_per_mpix=3000.0, policy="fifo")
     try:
         a = srv.submit(req(1024, 4), 256, 512)   # 1 unit, ~12.6 ms
         big = srv.submit(req(2048), 256, 512)    # the whole arena: must wait for a
@@ -420,6 +419,67 @@ def test_serve_size_aware_policy(policy):
         srv.close()
 
 
+def test_serve_chunked_small_request_overtakes_large():
+    """Chunked policy: a small request submitted while a large one runs waits
+    for at most two of the large one's chunks, not for the whole request, and
+    the large one only pauses (its latency grows by about the small one's
+    work, not twice as under sharing)."""
+    srv = api.Server(1 << 30, max_slots=4, mock_us_per_mpix=1500.0, policy="chunked")
+    try:
+        big = srv.submit(req(2048, 16), 256, 512)    # 4 chunks of 4: ~100 ms in all
+        time.sleep(0.01)
+        small = srv.submit(req(512), 256, 512)       # ~0.4 ms of work
+        for t in (big, small):
+            assert srv.wait(t, 10.0) == L.DOP_OK
+        lb, ls = srv.latency_ms(big), srv.latency_ms(small)
+        assert ls < 0.6 * lb          # at most two 25 ms chunks ahead of it
+        assert lb < 1.3 * 100.6       # the big one lost about 0.4 ms, no sharing
+    finally:
+        srv.close()
+
+
+def test_serve_chunked_age_bound_zero_is_oldest_first():
+    """With an age bound of 0 every request counts as aged: chunks go oldest
+    request first, so the small one finishes after the large one."""
+    srv = api.Server(1 << 30, max_slots=4, mock_us_per_mpix=1500.0, policy="chunked",
+                     age_bound_s=0.0)
+    try:
+        big = srv.submit(req(2048, 8), 256, 512)     # ~50 ms
+        time.sleep(0.005)
+        small = srv.submit(req(512), 256, 512)
+        for t in (big, small):
+            assert srv.wait(t, 10.0) == L.DOP_OK
+        assert srv.latency_ms(small) + 5.0 > srv.latency_ms(big)
+    finally:
+        srv.close()
+
+
+def test_serve_chunked_admission_goes_around_a_young_head():
+    """Chunked policy: while the head of the queue does not fit the arena and
+    is younger than the age bound, a later request that fits is admitted
+    ahead of it."""
+    srv = api.Server(ws(2048), max_slots=4, mock_us_per_mpix=3000.0, policy="chunked")
+    try:
+        a = srv.submit(req(1024, 4), 256, 512)   # one field (two exceed half the arena)
+        big = srv.submit(req(2048), 256, 512)    # the whole arena: must wait for a
+        c = srv.submit(req(1024), 256, 512)      # fits beside a: goes ahead of big
+        for t in (a, big, c):
+            assert srv.wait(t, 10.0) == L.DOP_OK
+        assert srv.latency_ms(c) < srv.latency_ms(big)
+    finally:
+        srv.close()
+
+
+def test_serve_chunked_groups_use_at_most_half_the_arena():
+    srv = api.Server(2 * ws(1024), max_slots=2, mock_us_per_mpix=100.0, policy="chunked")
+    try:
+        t = srv.submit(req(1024, 8), 256, 512)   # four fields would not fit half the arena
+        assert srv.wait(t, 10.0) == L.DOP_OK
+        assert srv.stats()["arena_peak"] == ws(1024)
+    finally:
+        srv.close()
+
+
 def test_serve_set_policy_validation():
     srv = api.Server(1 << 20, max_slots=1, mock_us_per_mpix=0.0)
     try:
@@ -428,5 +488,9 @@ def test_serve_set_policy_validation():
         assert lib().dop_serve_set_policy(srv.handle, 1, float("nan")) == L.DOP_ERR_INVALID_ARG
         assert lib().dop_serve_set_policy(None, 1, 0.25) == L.DOP_ERR_INVALID_ARG
         assert lib().dop_serve_set_policy(srv.handle, 1, 0.5) == L.DOP_OK
+        assert lib().dop_serve_set_policy(srv.handle, L.DOP_SERVE_CHUNKED, 0.0) == L.DOP_OK
+        assert lib().dop_serve_set_policy(srv.handle, L.DOP_SERVE_CHUNKED,
+                                          float("inf")) == L.DOP_ERR_INVALID_ARG
+        assert lib().dop_serve_set_policy(srv.handle, L.DOP_SERVE_FIFO, 0.0) == L.DOP_OK
     finally:
         srv.close()

@@ -49,13 +49,18 @@ def make_requests(api, count, seed):
     return reqs
 
 
-def test_serve_bitwise_alone_vs_mix(api):
+@pytest.mark.parametrize("policy", ["chunked", "fifo"])
+def test_serve_bitwise_alone_vs_mix(api, policy):
+    """Under the chunked policy a request runs in wavelength-group chunks
+    interleaved with other requests' chunks on one stream; under FIFO whole
+    requests run side by side on several streams.  Either way each PSF is
+    bitwise the one dop_psf computes for the request alone."""
     reqs = make_requests(api, 24, seed=7)
     alone = [api.psf(h, prob, amp=amp).clone() for prob, h, amp in reqs]
     torch.cuda.synchronize()
     # arena for about three of the largest workspaces: admission is memory-bound
     big = max(api.workspace_size(p) for p, _, _ in reqs)
-    srv = api.Server(3 * big, max_slots=4)
+    srv = api.Server(3 * big, max_slots=4, policy=policy)
     try:
         outs = [torch.full(p.out_shape, float("nan"), device="cuda") for p, _, _ in reqs]
         torch.cuda.synchronize()

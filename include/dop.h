@@ -187,6 +187,28 @@ dop_status dop_psf(dop_context *ctx, const dop_problem *prob, const float *h,
  * 67 run one wavelength at a time. */
 
 /*
+ * dop_psf for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation, arguments and result as dop_psf, bitwise, but the
+ * workspace is the library's own device scratch, a static array of
+ * DOP_NOALLOC_MAX_BYTES that each device holds until the process ends (its
+ * address is looked up once per device when a context is created).  The
+ * call allocates nothing and creates no events (it is not timed by
+ * dop_profile_*).  Problems whose workspace (dop_workspace_size with
+ * DOP_OP_PSF) exceeds DOP_NOALLOC_MAX_BYTES, i.e. grids larger than
+ * 4096 x 4096, are rejected with DOP_ERR_WORKSPACE before anything is
+ * enqueued; up to four wavelengths run as one group when their fields fit.
+ * All calls on one device share its scratch and leave their last contents
+ * in it: calls whose work overlaps on one device (different streams, or
+ * host threads without ordering) race and give wrong results.  Nothing in
+ * the scratch needs clearing between calls.
+ */
+#define DOP_NOALLOC_MAX_BYTES ((size_t)167772160) /* 160 MiB */
+
+dop_status dop_psf_noalloc(dop_context *ctx, const dop_problem *prob, const float *h,
+                           const float *amp, float *psf, void *saved_u, void *stream);
+
+/*
  * Gradient of a real loss L with respect to h, given grad_psf = dL/dPSF
  * (N x N float32, CROP only) and the fields saved by dop_psf (K x N x N c64).
  * Per wavelength: g_U = 2 w_k G U_k, g_E = adjoint of Eq. (3) applied to g_U

@@ -39,6 +39,7 @@ DOP_OUT_FULL = 1
 DOP_OP_PROPAGATE = 0
 DOP_OP_PSF = 1
 DOP_OP_PSF_BACKWARD = 2
+DOP_NOALLOC_MAX_BYTES = 167772160
 DOP_PROBE_READ = 0
 DOP_PROBE_WRITE = 1
 DOP_PROBE_COPY = 2
@@ -106,6 +107,7 @@ _SIGNATURES = {
     "dop_workspace_size": (ctypes.c_int, [_VP, _PROB, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "dop_propagate": (ctypes.c_int, [_VP, _PROB, ctypes.c_int, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     "dop_psf": (ctypes.c_int, [_VP, _PROB, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
+    "dop_psf_noalloc": (ctypes.c_int, [_VP, _PROB, _VP, _VP, _VP, _VP, _VP]),
     "dop_psf_backward": (ctypes.c_int, [_VP, _PROB, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     "dop_serve_create": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_VP)]),
     "dop_serve_create_mock": (ctypes.c_int, [_VP, ctypes.c_size_t, ctypes.c_int, ctypes.c_double,

@@ -260,6 +260,26 @@ def psf(h, prob, amp=None, save_fields=False, ctx=None, out=None, group=4):
     return (out, saved) if save_fields else out
 
 
+def psf_noalloc(h, prob, amp=None, out=None, saved=None, ctx=None):
+    """psf() through dop_psf_noalloc: the library's static device scratch is
+    the workspace, so the call allocates no device memory inside the library
+    (pass `out`, and `saved` for the fields, to allocate nothing here either).
+    Grids up to 4096 x 4096; calls that overlap on one device race."""
+    ctx = ctx or default_context(h.device.index)
+    dev = ctx.device
+    _need(h, "h", torch.float32, prob.h_shape, dev)
+    if amp is not None:
+        _need(amp, "amp", torch.float32, prob.doe_shape, dev)
+    if out is None:
+        out = torch.empty(prob.out_shape, dtype=torch.float32, device=h.device)
+    _need(out, "out", torch.float32, prob.out_shape, dev)
+    if saved is not None:
+        _need(saved, "saved", torch.complex64, (prob.k,) + prob.doe_shape, dev)
+    check(lib().dop_psf_noalloc(ctx.handle, prob.ptr(), _ptr(h), _ptr(amp), _ptr(out), _ptr(saved),
+                                ctypes.c_void_p(_stream_handle(dev))), "dop_psf_noalloc")
+    return out
+
+
 def psf_backward(h, prob, saved_u, grad_psf, amp=None, ctx=None, out=None):
     """dL/dh given dL/dPSF (crop) and the fields saved by psf(); dL/dh has
     the shape of h (the coarse design when upsampled)."""

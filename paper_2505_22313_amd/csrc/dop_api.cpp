@@ -14,9 +14,18 @@
 #include "dop_internal.h"
 #include "dop_host.h"
 
+// Scratch memory of the no-allocation entry point dop_psf_noalloc: the
+// workspace fields of problems up to DOP_NOALLOC_MAX_BYTES.  Each device the
+// library runs on holds its own copy until the process ends.  In host code
+// `scratch` names a host-side stand-in, not device memory: its address on
+// each device is looked up once (scratch_on_device) and only that address is
+// handed to kernels.
+static __device__ __align__(256) unsigned char scratch[DOP_NOALLOC_MAX_BYTES];
+
 struct dop_context {
   int device = 0;
   float2 *tw = nullptr;  // kTwN complex64 twiddles exp(-2 pi i j / kTwN)
+  void *scratch = nullptr;  // device address of `scratch` on this device
   // per-pass timing (off unless enabled)
   std::mutex prof_mu;
   bool prof_on = false;
@@ -46,6 +55,25 @@ dop_status fail(dop_status s, const char *fmt, ...) {
 }
 
 void clear_error() { g_last_error.clear(); }
+
+// Device address of `scratch` on `device`, which must be the current device:
+// looked up once per device and kept; NULL if the lookup failed.
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[kMaxDevices];
+
+static void *scratch_on_device(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess && ptr)
+      g_scratch_dev[device] = ptr;
+    else
+      (void)hipGetLastError();  // leave no sticky error behind
+  }
+  return g_scratch_dev[device];
+}
 
 static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 static bool aligned(const void *p, size_t a) { return reinterpret_cast<uintptr_t>(p) % a == 0; }
@@ -334,6 +362,9 @@ dop_status dop_context_create(int device, dop_context **out) {
   hipError_t e = hipMalloc(reinterpret_cast<void **>(&ctx->tw), sizeof(float2) * kTwN);
   if (e == hipSuccess)
     e = hipMemcpy(ctx->tw, host.data(), sizeof(float2) * kTwN, hipMemcpyHostToDevice);
+  // the no-allocation entry point's scratch on this device (NULL: that entry
+  // point reports the failure; everything else works without it)
+  if (e == hipSuccess) ctx->scratch = scratch_on_device(device);
   (void)hipSetDevice(prev);
   if (e != hipSuccess) {
     if (ctx->tw) (void)hipFree(ctx->tw);
@@ -526,6 +557,28 @@ dop_status dop_psf(dop_context *ctx, const dop_problem *prob, const float *h, co
   if ((s = check_ctx_device(ctx)) != DOP_OK) return s;
   return enqueue_psf(ctx, prob, h, amp, psf, saved_u, ws, ws_bytes,
                      static_cast<hipStream_t>(stream));
+}
+
+dop_status dop_psf_noalloc(dop_context *ctx, const dop_problem *prob, const float *h,
+                           const float *amp, float *psf, void *saved_u, void *stream) {
+  clear_error();
+  dop_status s = check_psf_args(ctx, prob, h, amp, psf, saved_u);
+  if (s != DOP_OK) return s;
+  const size_t need = workspace_bytes_op(prob, DOP_OP_PSF);
+  if (need > (size_t)DOP_NOALLOC_MAX_BYTES)
+    return fail(DOP_ERR_WORKSPACE,
+                "grid %d x %d needs %zu bytes of workspace; the scratch of dop_psf_noalloc holds "
+                "%zu bytes (grids up to 4096 x 4096)",
+                grid_rows(prob), grid_cols(prob), need, (size_t)DOP_NOALLOC_MAX_BYTES);
+  if (!ctx->scratch)
+    return fail(DOP_ERR_DEVICE, "the device scratch of dop_psf_noalloc is not available on "
+                "device %d", ctx->device);
+  if ((s = check_ctx_device(ctx)) != DOP_OK) return s;
+  // every workspace element a pass reads has been written earlier in the same
+  // call (pass A writes the input rows, pass B every row), so the scratch
+  // left by an earlier call needs no clearing; no timing events are created
+  return enqueue_psf(ctx, prob, h, amp, psf, saved_u, ctx->scratch, DOP_NOALLOC_MAX_BYTES,
+                     static_cast<hipStream_t>(stream), false);
 }
 
 dop_status dop_psf_backward(dop_context *ctx, const dop_problem *prob, const float *h,

@@ -173,6 +173,7 @@ def test_entry_points_reject_null_context():
     p = good()
     v = ctypes.c_void_p(4096)
     assert lib().dop_psf(None, p.ptr(), v, None, v, None, v, 1 << 30, None) == L.DOP_ERR_INVALID_ARG
+    assert lib().dop_psf_noalloc(None, p.ptr(), v, None, v, None, None) == L.DOP_ERR_INVALID_ARG
     assert lib().dop_propagate(None, p.ptr(), 0, v, v, v, 1 << 30, None) == L.DOP_ERR_INVALID_ARG
     assert lib().dop_psf_backward(None, p.ptr(), v, None, v, v, v, v, 1 << 30,
                                   None) == L.DOP_ERR_INVALID_ARG

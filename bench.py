@@ -171,8 +171,11 @@ def serve_measure(api, wl, torch, count, rate_hz, pool, slots=4, seed=5,
     # continuous batching, under each policy
     big = max(api.workspace_size(p) for _, p, _ in reqs)
 
-    def served(policy):
-        srv = api.Server(2 * slots * big, max_slots=slots, policy=policy)
+    def served(spec):
+        # "chunked" or "chunked:<age bound s>", "fifo", "size_aware"
+        policy, _, arg = spec.partition(":")
+        kw = {"age_bound_s": float(arg)} if arg else {}
+        srv = api.Server(2 * slots * big, max_slots=slots, policy=policy, **kw)
         tickets = [None] * len(reqs)
         t0 = time.perf_counter()
 
@@ -475,8 +478,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=400,
                     help="requests in the trace at 0.7 x capacity (the 200 req/s trace, "
                          "about 11 x overload, uses a quarter of them)")
-    ap.add_argument("--serve-policies", default="chunked,fifo",
-                    help="server policies to replay, the first reported as 'served'")
+    ap.add_argument("--serve-policies", default="chunked,chunked:0.5,fifo",
+                    help="server policies to replay (chunked[:age bound s], fifo, size_aware), "
+                         "the first reported as 'served'")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the upsampling / band-limit measurements")
     ap.add_argument("--calib-copy", action="store_true",

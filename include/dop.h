@@ -366,13 +366,15 @@ dop_status dop_serve_submit(dop_server *srv, const dop_problem *prob,
  *   DOP_SERVE_CHUNKED (default): a request runs in chunks of one wavelength
  *     group (up to four wavelengths; its workspace holds that many fields,
  *     at most half the arena, or one field when no more fits at admission).
- *     All chunks go through one in-order stream, two enqueued at a time;
- *     each time a chunk completes, the next is taken from the admitted
- *     request with the least work left (n_lambda not yet enqueued x my x m),
- *     except that requests older than the age bound (seconds since submit)
- *     go first, oldest first.  A request arriving while a large one runs
- *     waits for at most two chunks; the large one pauses but never shares
- *     the GPU.  Admission takes the head of the queue first; while the head
+ *     All chunks go through one in-order stream, two enqueued at a time
+ *     (up to eight while those hold under 1e8 padded pixels x wavelengths,
+ *     about a millisecond of work); each time a chunk completes, the next
+ *     is taken from the admitted request with the least work left
+ *     (n_lambda not yet enqueued x my x m), except that requests older than
+ *     the age bound (seconds since submit) go first, oldest first.  A
+ *     request arriving while a large one runs waits only for the chunks
+ *     already enqueued (two of a large grid's); the large one pauses but
+ *     never shares the GPU.  Admission takes the head of the queue first; while the head
  *     does not fit and is younger than the age bound, later requests that
  *     fit (among the next 32) may be admitted ahead of it.
  *   DOP_SERVE_FIFO: admission in submission order; a request's whole PSF is
@@ -384,7 +386,7 @@ enum { DOP_SERVE_FIFO = 0, DOP_SERVE_SIZE_AWARE = 1, DOP_SERVE_CHUNKED = 2 };
 
 /* Set the policy for requests not yet admitted (admitted ones finish under
  * the policy they were admitted with).  `param` (finite, >= 0) is the age
- * bound in seconds for DOP_SERVE_CHUNKED (default 0.5; 0 serves chunks
+ * bound in seconds for DOP_SERVE_CHUNKED (default 0.25; 0 serves chunks
  * oldest request first), share_ratio for DOP_SERVE_SIZE_AWARE (default
  * 0.25), and ignored for DOP_SERVE_FIFO. */
 dop_status dop_serve_set_policy(dop_server *srv, int policy, double param);

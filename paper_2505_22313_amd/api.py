@@ -408,7 +408,7 @@ class Server:
                 "chunked": L.DOP_SERVE_CHUNKED}
 
     def __init__(self, arena_bytes, max_slots=4, ctx=None, mock_us_per_mpix=None,
-                 policy="chunked", share_ratio=0.25, age_bound_s=0.5):
+                 policy="chunked", share_ratio=0.25, age_bound_s=0.25):
         self.mock = mock_us_per_mpix is not None
         h = ctypes.c_void_p()
         if self.mock:
@@ -427,7 +427,7 @@ class Server:
         self._keep = {}
         self.set_policy(policy, share_ratio=share_ratio, age_bound_s=age_bound_s)
 
-    def set_policy(self, policy, share_ratio=0.25, age_bound_s=0.5):
+    def set_policy(self, policy, share_ratio=0.25, age_bound_s=0.25):
         """Scheduling policy: "chunked" (its age bound in seconds), "fifo" or
         "size_aware" (its share ratio); see dop_serve_set_policy."""
         param = {"chunked": age_bound_s, "size_aware": share_ratio}.get(policy, 0.0)

@@ -9,14 +9,14 @@
 //  - DOP_SERVE_CHUNKED (default): a request's wavelengths run in chunks of
 //    one wavelength group (up to four wavelengths that share one read of the
 //    heights and one read-modify-write of the PSF).  Chunks of all admitted
-//    requests go through one in-order stream, at most kDepth enqueued at a
-//    time.  Each time a chunk completes, the next one is taken from the
-//    admitted request with the least work left (shortest remaining
-//    processing time), unless requests have waited longer than the age bound:
-//    then the oldest of those goes first.  A request that arrives while a
-//    large one runs waits for at most kDepth chunks instead of the whole
-//    large request, and the large one is never slowed by sharing the GPU: it
-//    only pauses.  Admission takes the head of the queue first; a request
+//    requests go through one in-order stream, two enqueued at a time (more
+//    while they hold under about a millisecond of work).  Each time a chunk
+//    completes, the next one is taken from the admitted request with the
+//    least work left (shortest remaining processing time), unless requests
+//    have waited longer than the age bound: then the oldest of those goes
+//    first.  A request that arrives while a large one runs waits for the
+//    chunks already enqueued instead of the whole large request, and the
+//    large one is never slowed by sharing the GPU: it only pauses.  Admission takes the head of the queue first; a request
 //    behind a head that does not fit yet may go ahead of it unless the head
 //    has passed the age bound.
 //  - DOP_SERVE_FIFO and DOP_SERVE_SIZE_AWARE: a request's whole PSF is
@@ -54,14 +54,19 @@ static double now_s() {
   return std::chrono::duration<double>(Clock::now().time_since_epoch()).count();
 }
 
-// Chunks enqueued ahead on the chunked policy's stream: one running and one
-// waiting behind it, so the GPU does not idle while the scheduler picks.
+// Chunks enqueued ahead on the chunked policy's stream: at least two (one
+// running, one waiting behind it, so the GPU does not idle while the
+// scheduler picks), and more, up to kMaxDepth, while the enqueued chunks hold
+// less than kMinQueued padded pixels x wavelengths (about 1 ms of work):
+// short chunks of small grids finish faster than the scheduler thread reacts.
 constexpr int kDepth = 2;
+constexpr int kMaxDepth = 8;
+constexpr double kMinQueued = 1e8;
 // Queue entries the chunked policy's admission looks at past a head that
 // does not fit yet.
 constexpr int kAdmitLookahead = 32;
 // Default age bound of the chunked policy (seconds).
-constexpr double kDefaultAgeBound = 0.5;
+constexpr double kDefaultAgeBound = 0.25;
 
 struct Request {
   uint64_t ticket = 0;
@@ -258,6 +263,7 @@ struct dop_server {
     Request *r;
     int k_end;
     int lane;
+    double work = 0.0;  // padded pixels x wavelengths
   };
 
   std::unique_ptr<Executor> ex;
@@ -423,15 +429,24 @@ struct dop_server {
 
   void feed(double now) {
     int on_lane0 = 0;
-    for (const Chunk &c : chunks)
-      if (c.r->chunked) ++on_lane0;
-    while (on_lane0 < kDepth) {
+    double queued = 0.0;
+    for (const Chunk &c : chunks) {
+      if (!c.r->chunked) continue;
+      ++on_lane0;
+      queued += c.work;
+    }
+    while (on_lane0 < kDepth || (on_lane0 < kMaxDepth && queued < kMinQueued)) {
       Request *r = pick(now);
       if (!r) return;
       const int k1 = std::min(r->prob.n_lambda, r->k_next + r->group);
+      const double w = (double)(k1 - r->k_next) * grid_cols(&r->prob) * (double)grid_rows(&r->prob);
       const size_t before = chunks.size();
       start_chunk(r, k1, 0);
-      if (chunks.size() > before) ++on_lane0;
+      if (chunks.size() > before) {
+        chunks.back().work = w;
+        ++on_lane0;
+        queued += w;
+      }
     }
   }
 
@@ -495,7 +510,7 @@ dop_status dop_serve_create(dop_context *ctx, void *arena, size_t arena_bytes, i
   if (reinterpret_cast<uintptr_t>(arena) % Arena::kAlign != 0)
     return fail(DOP_ERR_INVALID_ARG, "arena must be %zu-byte aligned", Arena::kAlign);
   if (max_slots < 1 || max_slots > 64) return fail(DOP_ERR_INVALID_ARG, "max_slots must be 1..64");
-  auto ex = std::make_unique<GpuExecutor>(ctx, max_slots, max_slots + kDepth);
+  auto ex = std::make_unique<GpuExecutor>(ctx, max_slots, max_slots + kMaxDepth);
   const dop_status s = ex->init();
   if (s != DOP_OK) return s;
   return make_server(std::move(ex), arena, arena_bytes, max_slots, out);
@@ -509,7 +524,7 @@ dop_status dop_serve_create_mock(void *arena, size_t arena_bytes, int max_slots,
   if (!arena || arena_bytes == 0) return fail(DOP_ERR_INVALID_ARG, "arena is empty");
   if (max_slots < 1 || max_slots > 64) return fail(DOP_ERR_INVALID_ARG, "max_slots must be 1..64");
   if (!(service_us_per_mpix >= 0.0)) return fail(DOP_ERR_INVALID_ARG, "service time must be >= 0");
-  return make_server(std::make_unique<MockExecutor>(max_slots, max_slots + kDepth,
+  return make_server(std::make_unique<MockExecutor>(max_slots, max_slots + kMaxDepth,
                                                     service_us_per_mpix),
                      arena, arena_bytes, max_slots, out);
 }

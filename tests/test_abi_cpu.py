@@ -422,19 +422,21 @@ def test_serve_size_aware_policy(policy):
 
 def test_serve_chunked_small_request_overtakes_large():
     """Chunked policy: a small request submitted while a large one runs waits
-    for at most two of the large one's chunks, not for the whole request, and
+    for at most the two chunks already enqueued, not for the whole request, and
     the large one only pauses (its latency grows by about the small one's
     work, not twice as under sharing)."""
-    srv = api.Server(1 << 30, max_slots=4, mock_us_per_mpix=1500.0, policy="chunked")
+    srv = api.Server(8 << 30, max_slots=4, mock_us_per_mpix=100.0, policy="chunked")
     try:
-        big = srv.submit(req(2048, 16), 256, 512)    # 4 chunks of 4: ~100 ms in all
+        # 4 chunks of 4 wavelengths, 268 Mpix*lambda (26.8 ms) each: two are
+        # enqueued at a time, since each holds more than ~1 ms of work
+        big = srv.submit(req(8192, 16), 256, 512)
         time.sleep(0.01)
-        small = srv.submit(req(512), 256, 512)       # ~0.4 ms of work
+        small = srv.submit(req(512), 256, 512)       # ~0.03 ms of work
         for t in (big, small):
             assert srv.wait(t, 10.0) == L.DOP_OK
         lb, ls = srv.latency_ms(big), srv.latency_ms(small)
-        assert ls < 0.6 * lb          # at most two 25 ms chunks ahead of it
-        assert lb < 1.3 * 100.6       # the big one lost about 0.4 ms, no sharing
+        assert ls < 0.6 * lb          # at most two 26.8 ms chunks ahead of it
+        assert lb < 1.3 * 107.4       # the big one lost its 0.03 ms, no sharing
     finally:
         srv.close()
 

@@ -337,7 +337,9 @@ __host__ __device__ constexpr int fwd_radix_p2(int L, int s) {
        : L == 128 ? (s == 0 ? 16 : 8)
        : L == 256 ? 16
        : L == 512 ? (s == 0 ? 16 : (s == 1 ? 8 : 4))
-       : (s == 0 ? 16 : 8);  // 1024
+       : L == 1024 ? (s == 0 ? 16 : 8)
+       : L == 2048 ? (s < 2 ? 16 : 8)
+       : 16;  // 4096 (whole rows and columns of the small-grid path)
 }
 
 __host__ __device__ constexpr int n15(int L) {
@@ -1536,6 +1538,162 @@ DOP_KERNEL(Plan<PID>::TA) void k_pass_a_inv(KParams p) {
     }
   }
 }
+
+// ---------------------------------------------------------------------------
+// Small-grid path (square power-of-two M <= kSmallMaxM), three passes:
+//   S1: M-point DFT over x of each of the N input rows (field formed from h
+//       on the fly, Eq. 1-2), written in natural frequency order;
+//   S2: for a run of columns, M-point DFT over y (rows >= N are zeros and not
+//       read), times H (Eq. 3), inverse DFT over y; only the rows the output
+//       needs are written back;
+//   S3: inverse M-point DFT over kx of those rows, then the output stage
+//       (|U|^2 accumulated into the PSF with the wavelength weight, Eq. 4,
+//       and the optional saved field).
+// A whole row or column fits in a block, so the 2-D FFT takes two sweeps
+// instead of the large path's digit passes, and the column pass touches
+// only the N rows that hold data.  At these sizes the field (<= 128 MiB)
+// stays in the Infinity Cache between passes, and the five large-path
+// launches were latency-bound.
+// ---------------------------------------------------------------------------
+template <int LM>
+struct SmallPlan {
+  static constexpr int M = 1 << LM;
+  static constexpr size_t PITCH = (size_t)M + kRowPad;
+  // rows per S1/S3 tile (a tile holds at least 2048 points) and threads
+  static constexpr int RB = M >= 2048 ? 1 : 2048 / M;
+  static constexpr int TR = cmax(64, RB * M / 16);
+  // columns per S2 tile (about 8192 points, at most 16 columns) and threads
+  static constexpr int C = cmin(16, cmax(1, 8192 / M));
+  static constexpr int SJ = C + 1;  // LDS row stride: conflict-free column walks
+  static constexpr int TC = cmax(64, M * C / 16);
+};
+
+// S1 / S3: one tile = RB rows of M points; the row DFT runs along x.
+// IN_PHASE forward (S1) or OUT_PSF inverse (S3, OUTM = OUT_PSF).
+template <int LM, bool INV>
+__global__ __launch_bounds__(SmallPlan<LM>::TR) void k_small_rows(KParams p) {
+  using S = SmallPlan<LM>;
+  constexpr int M = S::M, RB = S::RB, T = S::TR;
+  // element (x, r) of the tile at LDS x * RB + r: x fastest across threads
+  using G = Geo<M, RB, RB, 1, T, true>;
+  __shared__ float2 lds[M * RB];
+  __shared__ float2 tw[M];
+  for (int i = threadIdx.x; i < M; i += T) tw[i] = p.tw[i << (kTwLog - LM)];
+  const int nrows = INV ? p.nrows_out : p.nrows_in;
+  const int ntiles = (nrows + RB - 1) / RB;
+  const int n = p.n;
+  float2 dummy[1][1];
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int tid = loop_tid();
+    const int y0 = tile * RB;
+    const int nb = cmin(RB, nrows - y0);
+    __syncthreads();
+    if constexpr (!INV) {
+      // the DOE field (Eq. 1-2), zero past column n
+      auto ld = [&](int x, int r) {
+        if (x >= n) return make_float2(0.f, 0.f);
+        const int y = y0 + r;
+        const float hv = p.h[(size_t)(y >> p.up_log2) * p.nh + (x >> p.up_log2)];
+        const float a = p.amp ? p.amp[(size_t)y * n + x] : 1.f;
+        return cscale(doe_phase(hv, p.phase_turns), a);
+      };
+      auto st = [&](int kx, int r, float2 v) { p.ws[(size_t)(y0 + r) * S::PITCH + kx] = v; };
+      dft_tile<G, false, false, SRC_FN, SNK_FN, M>(lds, tw, ld, st, dummy, tid, nb);
+    } else {
+      auto ld = [&](int kx, int r) { return p.ws[(size_t)(y0 + r) * S::PITCH + kx]; };
+      // output stage: w is M^2 U (the inverse DFT's 1/M^2 is in the constants)
+      auto st = [&](int x, int r, float2 w) {
+        const int y = y0 + r;
+        long long idx;
+        if (p.full) {
+          const int ys = y + p.p0y, xs = x + p.p0x;
+          idx = (long long)(ys >= M ? ys - M : ys) * M + (xs >= M ? xs - M : xs);
+        } else {
+          if (x >= n) return;
+          idx = (long long)y * n + x;
+        }
+        const float accv = p.first ? 0.f : p.psf[idx];
+        p.psf[idx] = psf_add(accv, p.wk_m4, w);
+        if (p.saved_out) p.saved_out[idx] = cscale(w, p.inv_m2);
+      };
+      dft_tile<G, true, false, SRC_FN, SNK_FN, M>(lds, tw, ld, st, dummy, tid, nb);
+    }
+  }
+}
+
+// S2: one tile = C consecutive columns of M points; DFT over y, times H,
+// inverse DFT over y, rows < nrows_out written back.
+template <int LM>
+__global__ __launch_bounds__(SmallPlan<LM>::TC) void k_small_cols(KParams p) {
+  using S = SmallPlan<LM>;
+  constexpr int M = S::M, C = S::C, SJ = S::SJ, T = S::TC;
+  using G = Geo<M, C, SJ, 1, T, false>;
+  __shared__ float2 lds[M * SJ];
+  __shared__ float2 tw[M];
+  __shared__ double a2col[C];
+  for (int i = threadIdx.x; i < M; i += T) tw[i] = p.tw[i << (kTwLog - LM)];
+  constexpr int NT = M / C;
+  float2 dummy[1][1];
+  for (int tile = blockIdx.x; tile < NT; tile += gridDim.x) {
+    const int tid = loop_tid();
+    const int x0 = tile * C;
+    __syncthreads();
+    // frequency-x data of the tile's columns; read after the forward DFT,
+    // whose stage barriers order this write before them
+    for (int c = tid; c < C; c += T) a2col[c] = a2_eff(axis_freq(x0 + c, M, p.inv_mdx, p.flim_x, p));
+    auto ld = [&](int y, int c) {
+      return y < p.nrows_in ? p.ws[(size_t)y * S::PITCH + x0 + c] : make_float2(0.f, 0.f);
+    };
+    dft_tile<G, false, false, SRC_FN, SNK_LDS, M>(lds, tw, ld, NoStore{}, dummy, tid);
+    auto ld_h = [&](int ky, int c) {
+      const double a2y = a2_eff(axis_freq(ky, M, p.inv_mdy, p.flim_y, p));
+      return cmul(lds[ky * SJ + c], transfer(a2y, a2col[c], p));
+    };
+    auto st = [&](int y, int c, float2 v) {
+      if (y < p.nrows_out) p.ws[(size_t)y * S::PITCH + x0 + c] = v;
+    };
+    dft_tile<G, true, false, SRC_FN, SNK_FN, M>(lds, tw, ld_h, st, dummy, tid);
+  }
+}
+
+static inline void mark(hipEvent_t *ev, int i, hipStream_t s);
+
+template <int LM>
+static hipError_t launch_small_lm(const KParams &p, hipStream_t s, hipEvent_t *ev) {
+  using S = SmallPlan<LM>;
+  auto grid = [](long long tiles) {
+    return (unsigned)(tiles < 1 ? 1 : tiles < kMaxBlocks ? tiles : kMaxBlocks);
+  };
+  mark(ev, 0, s);
+  hipLaunchKernelGGL((k_small_rows<LM, false>), dim3(grid((p.nrows_in + S::RB - 1) / S::RB)),
+                     dim3(S::TR), 0, s, p);
+  mark(ev, 1, s);
+  hipLaunchKernelGGL(k_small_cols<LM>, dim3(grid(S::M / S::C)), dim3(S::TC), 0, s, p);
+  mark(ev, 2, s);
+  hipLaunchKernelGGL((k_small_rows<LM, true>), dim3(grid((p.nrows_out + S::RB - 1) / S::RB)),
+                     dim3(S::TR), 0, s, p);
+  mark(ev, 3, s);
+  return hipGetLastError();
+}
+
+bool small_path(int plan) { return plan >= kSmallMinLM && plan <= kSmallMaxLM; }
+
+hipError_t launch_small(const KParams &p, hipStream_t s, hipEvent_t *ev) {
+  if (p.in_mode != IN_PHASE || p.out_mode != OUT_PSF) return hipErrorInvalidValue;
+  switch (p.plan) {
+    case 4: return launch_small_lm<4>(p, s, ev);
+    case 5: return launch_small_lm<5>(p, s, ev);
+    case 6: return launch_small_lm<6>(p, s, ev);
+    case 7: return launch_small_lm<7>(p, s, ev);
+    case 8: return launch_small_lm<8>(p, s, ev);
+    case 9: return launch_small_lm<9>(p, s, ev);
+    case 10: return launch_small_lm<10>(p, s, ev);
+    case 11: return launch_small_lm<11>(p, s, ev);
+    case 12: return launch_small_lm<12>(p, s, ev);
+    default: return hipErrorInvalidValue;
+  }
+}
+static_assert(kSmallMinLM == 4 && kSmallMaxLM == 12, "one launch case per small grid");
 
 // ---------------------------------------------------------------------------
 // Ceiling probe with pass C's memory access pattern and none of its

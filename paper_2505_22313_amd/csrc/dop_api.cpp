@@ -30,10 +30,11 @@ struct dop_context {
   std::mutex prof_mu;
   bool prof_on = false;
   std::vector<hipEvent_t> prof_pool;            // idle events
-  // marks around launched passes first, first + 1, ... (one more event than passes)
+  // marks around launched passes: interval i (ev[i] -> ev[i + 1]) is pass
+  // slot[i] (one more event than passes)
   struct Pending {
     std::vector<hipEvent_t> ev;
-    int first;
+    std::vector<int> slot;
   };
   std::vector<Pending> pending;
   double prof_ms[dop::kNumPasses] = {0, 0, 0, 0, 0};
@@ -200,33 +201,59 @@ void fill_common(KParams &kp, const dop_context *ctx, const dop_problem *prob, i
   kp.field_elems = workspace_bytes(prob) / sizeof(float2);
 }
 
+// Timing events for `n` consecutive passes while profiling is on (empty
+// otherwise, or when `timed` is false).
+static dop_status take_events(dop_context *ctx, int n, bool timed, std::vector<hipEvent_t> *ev) {
+  if (!timed) return DOP_OK;
+  std::lock_guard<std::mutex> lk(ctx->prof_mu);
+  if (!ctx->prof_on) return DOP_OK;
+  while ((int)ev->size() < n + 1) {
+    hipEvent_t e = nullptr;
+    if (!ctx->prof_pool.empty()) {
+      e = ctx->prof_pool.back();
+      ctx->prof_pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      return fail(DOP_ERR_DEVICE, "hipEventCreate failed");
+    }
+    ev->push_back(e);
+  }
+  return DOP_OK;
+}
+
+static void keep_events(dop_context *ctx, std::vector<hipEvent_t> &ev, std::vector<int> slot) {
+  if (ev.empty()) return;
+  std::lock_guard<std::mutex> lk(ctx->prof_mu);
+  ctx->pending.push_back({std::move(ev), std::move(slot)});
+}
+
 // Enqueue passes first..last of kp (0 = A ... 4 = A'), bracketed by timing
 // events while profiling is on.
 dop_status launch_range(const dop_context *cctx, const KParams &kp, int first, int last,
                         hipStream_t stream, bool timed = true) {
   dop_context *ctx = const_cast<dop_context *>(cctx);
   std::vector<hipEvent_t> ev;
-  if (timed) {
-    std::lock_guard<std::mutex> lk(ctx->prof_mu);
-    if (ctx->prof_on) {
-      while ((int)ev.size() < last - first + 2) {
-        hipEvent_t e = nullptr;
-        if (!ctx->prof_pool.empty()) {
-          e = ctx->prof_pool.back();
-          ctx->prof_pool.pop_back();
-        } else if (hipEventCreate(&e) != hipSuccess) {
-          return fail(DOP_ERR_DEVICE, "hipEventCreate failed");
-        }
-        ev.push_back(e);
-      }
-    }
-  }
+  dop_status s = take_events(ctx, last - first + 1, timed, &ev);
+  if (s != DOP_OK) return s;
   const hipError_t e = launch_passes(kp, first, last, stream, ev.empty() ? nullptr : ev.data());
-  if (!ev.empty()) {
-    std::lock_guard<std::mutex> lk(ctx->prof_mu);
-    ctx->pending.push_back({std::move(ev), first});
-  }
+  std::vector<int> slot;
+  for (int i = first; i <= last; ++i) slot.push_back(i);
+  keep_events(ctx, ev, std::move(slot));
   if (e != hipSuccess) return fail(DOP_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return DOP_OK;
+}
+
+// One wavelength of the small-grid path (rows, columns with H, rows); its
+// passes are timed as pass_a_fwd, pass_c and pass_a_inv.
+static dop_status launch_small_wavelength(const dop_context *cctx, const KParams &kp,
+                                          hipStream_t stream, bool timed) {
+  dop_context *ctx = const_cast<dop_context *>(cctx);
+  std::vector<hipEvent_t> ev;
+  dop_status s = take_events(ctx, 3, timed, &ev);
+  if (s != DOP_OK) return s;
+  const hipError_t e = launch_small(kp, stream, ev.empty() ? nullptr : ev.data());
+  keep_events(ctx, ev, {0, 2, 4});
+  if (e != hipSuccess)
+    return fail(DOP_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
   return DOP_OK;
 }
 
@@ -244,7 +271,7 @@ dop_status check_ctx_device(const dop_context *ctx) {
 }
 
 int psf_group(const dop_problem *prob, const void *saved_u, size_t ws_bytes) {
-  if (saved_u) return 1;
+  if (saved_u || small_path(plan_id(grid_cols(prob), grid_rows(prob)))) return 1;
   const size_t field = workspace_bytes(prob);
   const int g = plan_max_group(plan_id(grid_cols(prob), grid_rows(prob)));
   const size_t fit = ws_bytes / field;
@@ -282,7 +309,9 @@ dop_status enqueue_psf_range(const dop_context *ctx, const dop_problem *prob, in
       setup(kp, k0, ws);
       kp.first = (k0 == 0);
       kp.saved_out = saved_u ? static_cast<float2 *>(saved_u) + (size_t)k0 * nn : nullptr;
-      const dop_status s = launch_range(ctx, kp, 0, kNumPasses - 1, stream, timed);
+      const dop_status s = small_path(kp.plan)
+                               ? launch_small_wavelength(ctx, kp, stream, timed)
+                               : launch_range(ctx, kp, 0, kNumPasses - 1, stream, timed);
       if (s != DOP_OK) return s;
     } else {
       // a group: pass A forms the gk fields from one read of the heights,
@@ -406,8 +435,8 @@ static dop_status collect(dop_context *ctx) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, v[i], v[i + 1]) != hipSuccess)
         return fail(DOP_ERR_DEVICE, "hipEventElapsedTime failed");
-      ctx->prof_ms[pl.first + i] += ms;
-      ctx->prof_n[pl.first + i] += 1;
+      ctx->prof_ms[pl.slot[i]] += ms;
+      ctx->prof_n[pl.slot[i]] += 1;
     }
     for (hipEvent_t e : v) ctx->prof_pool.push_back(e);
   }

@@ -95,6 +95,16 @@ hipError_t launch_wavelength(const KParams &p, hipStream_t stream, hipEvent_t *e
 hipError_t launch_passes(const KParams &p, int first, int last, hipStream_t stream,
                          hipEvent_t *ev);
 
+// Small-grid path: square power-of-two grids of 2^kSmallMinLM .. 2^kSmallMaxLM
+// points per side run the PSF (IN_PHASE / OUT_PSF only) as three passes:
+// rows, columns with H, rows.  small_path(plan) says whether a plan id is
+// one of them; launch_small enqueues one wavelength's three passes, with
+// ev[0..3] (if not NULL) recorded before, between and after them.
+constexpr int kSmallMinLM = 4;
+constexpr int kSmallMaxLM = 12;
+bool small_path(int plan);
+hipError_t launch_small(const KParams &p, hipStream_t stream, hipEvent_t *ev);
+
 // Largest wavelength group the plan supports (1 if pass A' ends in a
 // radix-67 stage), 0 for an unknown plan.
 int plan_max_group(int plan);

@@ -1015,9 +1015,15 @@ DOP_KERNEL(Plan<PID>::TA) void k_pass_a_fwd(KParams p) {
   // (h, amp) for IN_PHASE, the field for IN_FIELD, the saved field for
   // IN_GRAD; columns x >= n are zero.
   float2 pre[FS::PER][FS::R];
+  // A tile is one input row: its arrays are addressed as a tile-uniform row
+  // base plus a 32-bit byte offset per element.
   auto fetch = [&](int tile, int tid) {
-    const size_t rowin = (size_t)(tile / RUNS) * n;
-    const size_t rowh = (size_t)((tile / RUNS) >> p.up_log2) * p.nh;
+    const int y = tile / RUNS;
+    const size_t rowin = (size_t)y * n;
+    const float *hrow = p.h + (size_t)(y >> p.up_log2) * p.nh;
+    const float *arow = p.amp ? p.amp + rowin : nullptr;
+    const float2 *frow = INM == IN_FIELD ? p.u_in + rowin : INM == IN_GRAD ? p.saved_in + rowin
+                                                                          : nullptr;
     const int xb0 = (tile % RUNS) * RA;
 #pragma unroll
     for (int i = 0; i < FS::PER; ++i) {
@@ -1030,11 +1036,11 @@ DOP_KERNEL(Plan<PID>::TA) void k_pass_a_fwd(KParams p) {
           const int x = BX * (j + t * FS::LR) + xb0 + b;
           float2 v = make_float2(0.f, 0.f);
           if (x < n) {
-            const size_t idx = rowin + x;
+            const unsigned ux = (unsigned)x;
             if constexpr (INM == IN_PHASE)
-              v = make_float2(p.h[rowh + (x >> p.up_log2)], p.amp ? p.amp[idx] : 1.f);
-            else if constexpr (INM == IN_FIELD) v = p.u_in[idx];
-            else v = p.saved_in[idx];
+              v = make_float2(*at_byte(hrow, (ux >> p.up_log2) * 4u),
+                              arow ? *at_byte(arow, ux * 4u) : 1.f);
+            else v = *at_byte(frow, ux * 8u);
           }
           pre[i][t] = v;
         }
@@ -1420,31 +1426,64 @@ DOP_KERNEL(Plan<PID>::TA) void k_pass_a_inv(KParams p) {
       }
     }
   };
-  // output index of element (xa, b) of the current tile, or -1 if outside
-  auto out_index = [&](int y, int xb0, int xa, int b) -> long long {
+  // A tile is one row y, so every output array is addressed as a
+  // tile-uniform row base plus a 32-bit column offset.  Element offset of
+  // the output row of row y (full plane: centred, wrapped):
+  auto out_row = [&](int y) -> size_t {
+    if (p.full) {
+      const int ys = y + p.p0y;  // < 2 My
+      return (size_t)(ys >= MY ? ys - MY : ys) * MX;
+    }
+    return (size_t)y * n;
+  };
+  // output column of element (xa, b) of the current tile; false if outside
+  auto out_col = [&](int xb0, int xa, int b, unsigned &c) {
     const int x = BX * xa + xb0 + b;
     if (p.full) {
-      const int ys = y + p.p0y, xs = x + p.p0x;  // ys < 2 My, xs < 2 Mx
-      const int yo = ys >= MY ? ys - MY : ys, xo = xs >= MX ? xs - MX : xs;
-      return (long long)yo * MX + xo;
+      const int xs = x + p.p0x;  // < 2 Mx
+      c = (unsigned)(xs >= MX ? xs - MX : xs);
+      return true;
     }
-    return x < n ? (long long)y * n + x : -1;
+    c = (unsigned)x;
+    return x < n;
   };
-  // output stage of one element: w is My Mx U (the inverse DFT's 1/(My Mx)
-  // is applied here), accv the accumulator value it adds to, wk the PSF weight
-  auto finish = [&](int y, int x, long long idx, float2 w, float accv, float wk) {
+  // Row bases of the outputs (and, for the gradient, of h and amp).
+  struct Rows {
+    float *acc;         // PSF or gradient row
+    float2 *field;      // saved or output field row (NULL if none)
+    const float *h;     // height row (gradient)
+    const float *amp;   // aperture row (gradient, NULL if none)
+  };
+  auto rows_of = [&](int y) {
+    const size_t r = out_row(y);
+    Rows o{nullptr, nullptr, nullptr, nullptr};
     if constexpr (OUTM == OUT_PSF) {
-      p.psf[idx] = psf_add(accv, wk, w);
-      if (p.saved_out) p.saved_out[idx] = cscale(w, p.inv_m2);
+      o.acc = p.psf + r;
+      if (p.saved_out) o.field = p.saved_out + r;
     } else if constexpr (OUTM == OUT_FIELD) {
-      p.u_out[idx] = cscale(w, p.inv_m2);
+      o.field = p.u_out + r;
     } else {
-      // crop only: x < n here
-      float2 e = doe_phase(p.h[(size_t)(y >> p.up_log2) * p.nh + (x >> p.up_log2)],
-                           p.phase_turns);
-      if (p.amp) e = cscale(e, p.amp[idx]);
+      o.acc = p.grad_h + r;
+      o.h = p.h + (size_t)(y >> p.up_log2) * p.nh;
+      if (p.amp) o.amp = p.amp + r;
+    }
+    return o;
+  };
+  // output stage of one element at column c: w is My Mx U (the inverse DFT's
+  // 1/(My Mx) is applied here), accv the accumulator value it adds to, wk
+  // the PSF weight
+  auto finish = [&](const Rows &o, unsigned c, float2 w, float accv, float wk) {
+    if constexpr (OUTM == OUT_PSF) {
+      *at_byte(o.acc, c * 4u) = psf_add(accv, wk, w);
+      if (o.field) *at_byte(o.field, c * 8u) = cscale(w, p.inv_m2);
+    } else if constexpr (OUTM == OUT_FIELD) {
+      *at_byte(o.field, c * 8u) = cscale(w, p.inv_m2);
+    } else {
+      // crop only: the column is x < n
+      float2 e = doe_phase(o.h[c >> p.up_log2], p.phase_turns);
+      if (o.amp) e = cscale(e, *at_byte(o.amp, c * 4u));
       // c_k Im(g_E conj(E)), g_E = w / (My Mx)
-      p.grad_h[idx] = accv + p.ck_m2 * (w.y * e.x - w.x * e.y);
+      *at_byte(o.acc, c * 4u) = accv + p.ck_m2 * (w.y * e.x - w.x * e.y);
     }
   };
   constexpr int CH = RUNS < 4 ? RUNS : 4;
@@ -1456,6 +1495,7 @@ DOP_KERNEL(Plan<PID>::TA) void k_pass_a_inv(KParams p) {
     if (tile < 0) continue;
     const int y = tile / RUNS;
     const int xb0 = (tile % RUNS) * RA;
+    const Rows orow = rows_of(y);
     float acc[APER][AR];
     for (int q = 0; q < ngroup; ++q) {
       const int tid = loop_tid();
@@ -1489,10 +1529,10 @@ DOP_KERNEL(Plan<PID>::TA) void k_pass_a_inv(KParams p) {
 #pragma unroll
               for (int t = 0; t < LS::R; ++t) {
                 acc[i][t] = 0.f;
-                if (accumulate && (SSL::EXACT || it < SSL::ITEMS)) {
-                  const long long idx = out_index(y, xb0, j + t * LRL, b);
-                  if (idx >= 0) acc[i][t] = (OUTM == OUT_PSF) ? p.psf[idx] : p.grad_h[idx];
-                }
+                unsigned c;
+                if (accumulate && (SSL::EXACT || it < SSL::ITEMS) &&
+                    out_col(xb0, j + t * LRL, b, c))
+                  acc[i][t] = *at_byte(orow.acc, c * 4u);
               }
             }
           }
@@ -1507,10 +1547,10 @@ DOP_KERNEL(Plan<PID>::TA) void k_pass_a_inv(KParams p) {
       if constexpr (VIA_FN) {
         float2 dummy[1][1];
         auto st = [&](int xa, int b, float2 w) {
-          const long long idx = out_index(y, xb0, xa, b);
-          if (idx < 0) return;
-          const float accv = !accumulate ? 0.f : (OUTM == OUT_PSF) ? p.psf[idx] : p.grad_h[idx];
-          finish(y, BX * xa + xb0 + b, idx, w, accv, wk);
+          unsigned c;
+          if (!out_col(xb0, xa, b, c)) return;
+          const float accv = accumulate ? *at_byte(orow.acc, c * 4u) : 0.f;
+          finish(orow, c, w, accv, wk);
         };
         dft_tile_hooked<G, true, false, SRC_REG, SNK_FN, P::THI>(lds, tw.hi, NoLoad{}, st, hook, v,
                                                                 dummy, tid);
@@ -1527,9 +1567,9 @@ DOP_KERNEL(Plan<PID>::TA) void k_pass_a_inv(KParams p) {
             decode_item<G, LS::R>(it, j, b);
 #pragma unroll
             for (int t = 0; t < LS::R; ++t) {
-              const long long idx = out_index(y, xb0, j + t * LRL, b);
-              if (idx < 0) continue;
-              if (last) finish(y, BX * (j + t * LRL) + xb0 + b, idx, u[i][t], acc[i][t], wk);
+              unsigned c;
+              if (!out_col(xb0, j + t * LRL, b, c)) continue;
+              if (last) finish(orow, c, u[i][t], acc[i][t], wk);
               else acc[i][t] = psf_add(acc[i][t], wk, u[i][t]);
             }
           }
@@ -1540,7 +1580,7 @@ DOP_KERNEL(Plan<PID>::TA) void k_pass_a_inv(KParams p) {
 }
 
 // ---------------------------------------------------------------------------
-// Small-grid path (square power-of-two M <= kSmallMaxM), three passes:
+// Small-grid path (square power-of-two M up to 2048), three passes:
 //   S1: M-point DFT over x of each of the N input rows (field formed from h
 //       on the fly, Eq. 1-2), written in natural frequency order;
 //   S2: for a run of columns, M-point DFT over y (rows >= N are zeros and not
@@ -1551,19 +1591,22 @@ DOP_KERNEL(Plan<PID>::TA) void k_pass_a_inv(KParams p) {
 //       and the optional saved field).
 // A whole row or column fits in a block, so the 2-D FFT takes two sweeps
 // instead of the large path's digit passes, and the column pass touches
-// only the N rows that hold data.  At these sizes the field (<= 128 MiB)
+// only the N rows that hold data.  At these sizes the field (<= 32 MiB)
 // stays in the Infinity Cache between passes, and the five large-path
-// launches were latency-bound.
+// launches were latency-bound.  At 4096 the column pass, limited to two
+// columns (16-byte runs) by the LDS, was twice as slow as the large path.
 // ---------------------------------------------------------------------------
 template <int LM>
 struct SmallPlan {
   static constexpr int M = 1 << LM;
   static constexpr size_t PITCH = (size_t)M + kRowPad;
-  // rows per S1/S3 tile (a tile holds at least 2048 points) and threads
-  static constexpr int RB = M >= 2048 ? 1 : 2048 / M;
+  // rows per S1/S3 tile (at least 512 points) and threads; at these sizes
+  // the passes are latency-bound, so tiles are kept small and numerous
+  static constexpr int RB = M >= 512 ? 1 : 512 / M;
   static constexpr int TR = cmax(64, RB * M / 16);
-  // columns per S2 tile (about 8192 points, at most 16 columns) and threads
-  static constexpr int C = cmin(16, cmax(1, 8192 / M));
+  // columns per S2 tile: M / 256 (so that there are 256 tiles), at least 1
+  // and at most 4
+  static constexpr int C = cmin(4, cmax(1, M / 256));
   static constexpr int SJ = C + 1;  // LDS row stride: conflict-free column walks
   static constexpr int TC = cmax(64, M * C / 16);
 };
@@ -1689,11 +1732,10 @@ hipError_t launch_small(const KParams &p, hipStream_t s, hipEvent_t *ev) {
     case 9: return launch_small_lm<9>(p, s, ev);
     case 10: return launch_small_lm<10>(p, s, ev);
     case 11: return launch_small_lm<11>(p, s, ev);
-    case 12: return launch_small_lm<12>(p, s, ev);
     default: return hipErrorInvalidValue;
   }
 }
-static_assert(kSmallMinLM == 4 && kSmallMaxLM == 12, "one launch case per small grid");
+static_assert(kSmallMinLM == 4 && kSmallMaxLM == 11, "one launch case per small grid");
 
 // ---------------------------------------------------------------------------
 // Ceiling probe with pass C's memory access pattern and none of its

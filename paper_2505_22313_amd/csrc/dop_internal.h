@@ -101,7 +101,7 @@ hipError_t launch_passes(const KParams &p, int first, int last, hipStream_t stre
 // one of them; launch_small enqueues one wavelength's three passes, with
 // ev[0..3] (if not NULL) recorded before, between and after them.
 constexpr int kSmallMinLM = 4;
-constexpr int kSmallMaxLM = 12;
+constexpr int kSmallMaxLM = 11;
 bool small_path(int plan);
 hipError_t launch_small(const KParams &p, hipStream_t stream, hipEvent_t *ev);
 

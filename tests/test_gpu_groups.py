@@ -6,7 +6,7 @@ identical; checked over wavelength counts that leave partial groups, square,
 non-power-of-two and rectangular grids, CROP and FULL, weights, amp, the band
 limit and the fused upsampling, plus a grid whose pass A' ends in a radix-67
 stage (no grouping there).  The launch counts show the grouping.  Square
-power-of-two grids up to 4096 run the three-pass small-grid path, which does
+power-of-two grids up to 2048 run the three-pass small-grid path, which does
 not group wavelengths: there both calls run the same passes."""
 
 import numpy as np
@@ -61,9 +61,9 @@ def test_grouped_psf_is_bitwise_per_wavelength(api, n, m, k, mode, bl, up, amp):
     prof = ctx.profile_read()
     ctx.profile_enable(False)
     assert torch.equal(one, grouped)
-    # square power-of-two grids up to 4096 take the three-pass small-grid
+    # square power-of-two grids up to 2048 take the three-pass small-grid
     # path, one wavelength at a time; the radix-67 grid is not grouped either
-    small = np.ndim(m) == 0 and m <= 4096 and m & (m - 1) == 0
+    small = np.ndim(m) == 0 and m <= 2048 and m & (m - 1) == 0
     groups = k if small or nx in (1500,) else -(-k // 4)
     assert prof["pass_a_fwd"][0] == groups and prof["pass_a_inv"][0] == groups
     assert prof["pass_c"][0] == k

@@ -1600,16 +1600,65 @@ template <int LM>
 struct SmallPlan {
   static constexpr int M = 1 << LM;
   static constexpr size_t PITCH = (size_t)M + kRowPad;
+  // points per thread: 8 below 2048 (more waves to hide the latency chain of
+  // these small tiles), 16 at 2048 (measured equal or better there)
+  static constexpr int PPT = M >= 2048 ? 16 : 8;
   // rows per S1/S3 tile (at least 512 points) and threads; at these sizes
   // the passes are latency-bound, so tiles are kept small and numerous
   static constexpr int RB = M >= 512 ? 1 : 512 / M;
-  static constexpr int TR = cmax(64, RB * M / 16);
+  static constexpr int TR = cmax(64, RB * M / PPT);
   // columns per S2 tile: M / 256 (so that there are 256 tiles), at least 1
   // and at most 4
   static constexpr int C = cmin(4, cmax(1, M / 256));
   static constexpr int SJ = C + 1;  // LDS row stride: conflict-free column walks
-  static constexpr int TC = cmax(64, M * C / 16);
+  static constexpr int TC = cmax(64, M * C / PPT);
 };
+
+// The twiddle table omega_M^i, i < M, read into registers (loads issued, not
+// yet waited for) and then written to LDS.
+template <int LM, int T>
+struct SmallTw {
+  static constexpr int M = 1 << LM, N = (M + T - 1) / T;
+  float2 r[N];
+  DEV void load(const float2 *g) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      const int i = (int)threadIdx.x + q * T;
+      if (M % T == 0 || i < M) r[q] = g[i << (kTwLog - LM)];
+    }
+  }
+  DEV void put(float2 *tw) const {
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      const int i = (int)threadIdx.x + q * T;
+      if (M % T == 0 || i < M) tw[i] = r[q];
+    }
+  }
+};
+
+// The first Stockham stage's inputs of a tile gathered into registers, in
+// the layout a register-fed first stage consumes (only the items it will
+// use: b < nb_act).  Issued together with the twiddle loads, so the two
+// memory latencies overlap instead of following each other; ld must not
+// branch around its loads (clamp the address and select instead), so that
+// all of an item's loads are in flight before the first is waited for.
+template <class G, class LoadF>
+DEV void gather_first(float2 (&pre)[FirstStage<G>::PER][FirstStage<G>::R], const LoadF &ld,
+                      const int tid, const int nb_act) {
+  using FS = FirstStage<G>;
+#pragma unroll
+  for (int i = 0; i < FS::PER; ++i) {
+    const int it = tid + i * G::T;
+    if (FS::EXACT || it < FS::ITEMS) {
+      int j, b;
+      decode_item<G, FS::R>(it, j, b);
+      if (b < nb_act) {
+#pragma unroll
+        for (int t = 0; t < FS::R; ++t) pre[i][t] = ld(j + t * FS::LR, b);
+      }
+    }
+  }
+}
 
 // S1 / S3: one tile = RB rows of M points; the row DFT runs along x.
 // IN_PHASE forward (S1) or OUT_PSF inverse (S3, OUTM = OUT_PSF).
@@ -1619,31 +1668,52 @@ __global__ __launch_bounds__(SmallPlan<LM>::TR) void k_small_rows(KParams p) {
   constexpr int M = S::M, RB = S::RB, T = S::TR;
   // element (x, r) of the tile at LDS x * RB + r: x fastest across threads
   using G = Geo<M, RB, RB, 1, T, true>;
+  using FS = FirstStage<G>;
   __shared__ float2 lds[M * RB];
   __shared__ float2 tw[M];
-  for (int i = threadIdx.x; i < M; i += T) tw[i] = p.tw[i << (kTwLog - LM)];
   const int nrows = INV ? p.nrows_out : p.nrows_in;
   const int ntiles = (nrows + RB - 1) / RB;
   const int n = p.n;
-  float2 dummy[1][1];
+  // forward (S1): the DOE field (Eq. 1-2), zero past column n.  Branch-free:
+  // columns past n read column 0 and are replaced by zero; without an
+  // amplitude the amplitude load reads h[0] and is replaced by one.
+  const float *amp_src = p.amp ? p.amp : p.h;
+  auto ld_doe = [&](int y0, int x, int r) {
+    const bool in = x < n;
+    const int xc = in ? x : 0;
+    const int y = y0 + r;
+    const float hv = p.h[(size_t)(y >> p.up_log2) * p.nh + (xc >> p.up_log2)];
+    const float av = amp_src[p.amp ? (size_t)y * n + xc : 0];
+    const float a = p.amp ? av : 1.f;
+    const float2 v = cscale(doe_phase(hv, p.phase_turns), a);
+    return in ? v : make_float2(0.f, 0.f);
+  };
+  // inverse (S3): the spectrum rows left by S2
+  auto ld_ws = [&](int y0, int kx, int r) { return p.ws[(size_t)(y0 + r) * S::PITCH + kx]; };
+  auto gather = [&](int tile, float2 (&pre)[FS::PER][FS::R], int tid) {
+    const int y0 = tile * RB, nb = cmin(RB, nrows - y0);
+    if constexpr (!INV)
+      gather_first<G>(pre, [&](int x, int r) { return ld_doe(y0, x, r); }, tid, nb);
+    else
+      gather_first<G>(pre, [&](int kx, int r) { return ld_ws(y0, kx, r); }, tid, nb);
+  };
+  SmallTw<LM, T> twr;
+  twr.load(p.tw);
+  float2 pre[FS::PER][FS::R];
+  if ((int)blockIdx.x < ntiles) gather(blockIdx.x, pre, threadIdx.x);
+  twr.put(tw);  // read from the second stage on, after the first's barriers
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int tid = loop_tid();
     const int y0 = tile * RB;
     const int nb = cmin(RB, nrows - y0);
-    __syncthreads();
+    if (tile != (int)blockIdx.x) {
+      __syncthreads();
+      gather(tile, pre, tid);
+    }
     if constexpr (!INV) {
-      // the DOE field (Eq. 1-2), zero past column n
-      auto ld = [&](int x, int r) {
-        if (x >= n) return make_float2(0.f, 0.f);
-        const int y = y0 + r;
-        const float hv = p.h[(size_t)(y >> p.up_log2) * p.nh + (x >> p.up_log2)];
-        const float a = p.amp ? p.amp[(size_t)y * n + x] : 1.f;
-        return cscale(doe_phase(hv, p.phase_turns), a);
-      };
       auto st = [&](int kx, int r, float2 v) { p.ws[(size_t)(y0 + r) * S::PITCH + kx] = v; };
-      dft_tile<G, false, false, SRC_FN, SNK_FN, M>(lds, tw, ld, st, dummy, tid, nb);
+      dft_tile<G, false, false, SRC_REG, SNK_FN, M>(lds, tw, NoLoad{}, st, pre, tid, nb);
     } else {
-      auto ld = [&](int kx, int r) { return p.ws[(size_t)(y0 + r) * S::PITCH + kx]; };
       // output stage: w is M^2 U (the inverse DFT's 1/M^2 is in the constants)
       auto st = [&](int x, int r, float2 w) {
         const int y = y0 + r;
@@ -1659,7 +1729,7 @@ __global__ __launch_bounds__(SmallPlan<LM>::TR) void k_small_rows(KParams p) {
         p.psf[idx] = psf_add(accv, p.wk_m4, w);
         if (p.saved_out) p.saved_out[idx] = cscale(w, p.inv_m2);
       };
-      dft_tile<G, true, false, SRC_FN, SNK_FN, M>(lds, tw, ld, st, dummy, tid, nb);
+      dft_tile<G, true, false, SRC_REG, SNK_FN, M>(lds, tw, NoLoad{}, st, pre, tid, nb);
     }
   }
 }
@@ -1671,23 +1741,37 @@ __global__ __launch_bounds__(SmallPlan<LM>::TC) void k_small_cols(KParams p) {
   using S = SmallPlan<LM>;
   constexpr int M = S::M, C = S::C, SJ = S::SJ, T = S::TC;
   using G = Geo<M, C, SJ, 1, T, false>;
+  using FS = FirstStage<G>;
   __shared__ float2 lds[M * SJ];
   __shared__ float2 tw[M];
   __shared__ double a2col[C];
-  for (int i = threadIdx.x; i < M; i += T) tw[i] = p.tw[i << (kTwLog - LM)];
   constexpr int NT = M / C;
-  float2 dummy[1][1];
+  auto gather = [&](int tile, float2 (&pre)[FS::PER][FS::R], int tid) {
+    const int x0 = tile * C;
+    // rows at or past nrows_in are zero: read row 0 and replace (branch-free)
+    auto ld = [&](int y, int c) {
+      const bool in = y < p.nrows_in;
+      const float2 v = p.ws[(size_t)(in ? y : 0) * S::PITCH + x0 + c];
+      return in ? v : make_float2(0.f, 0.f);
+    };
+    gather_first<G>(pre, ld, tid, C);
+  };
+  SmallTw<LM, T> twr;
+  twr.load(p.tw);
+  float2 pre[FS::PER][FS::R];
+  if ((int)blockIdx.x < NT) gather(blockIdx.x, pre, threadIdx.x);
+  twr.put(tw);  // read from the second stage on, after the first's barriers
   for (int tile = blockIdx.x; tile < NT; tile += gridDim.x) {
     const int tid = loop_tid();
     const int x0 = tile * C;
-    __syncthreads();
+    if (tile != (int)blockIdx.x) {
+      __syncthreads();
+      gather(tile, pre, tid);
+    }
     // frequency-x data of the tile's columns; read after the forward DFT,
     // whose stage barriers order this write before them
     for (int c = tid; c < C; c += T) a2col[c] = a2_eff(axis_freq(x0 + c, M, p.inv_mdx, p.flim_x, p));
-    auto ld = [&](int y, int c) {
-      return y < p.nrows_in ? p.ws[(size_t)y * S::PITCH + x0 + c] : make_float2(0.f, 0.f);
-    };
-    dft_tile<G, false, false, SRC_FN, SNK_LDS, M>(lds, tw, ld, NoStore{}, dummy, tid);
+    dft_tile<G, false, false, SRC_REG, SNK_LDS, M>(lds, tw, NoLoad{}, NoStore{}, pre, tid);
     auto ld_h = [&](int ky, int c) {
       const double a2y = a2_eff(axis_freq(ky, M, p.inv_mdy, p.flim_y, p));
       return cmul(lds[ky * SJ + c], transfer(a2y, a2col[c], p));
@@ -1695,6 +1779,7 @@ __global__ __launch_bounds__(SmallPlan<LM>::TC) void k_small_cols(KParams p) {
     auto st = [&](int y, int c, float2 v) {
       if (y < p.nrows_out) p.ws[(size_t)y * S::PITCH + x0 + c] = v;
     };
+    float2 dummy[1][1];
     dft_tile<G, true, false, SRC_FN, SNK_FN, M>(lds, tw, ld_h, st, dummy, tid);
   }
 }

@@ -82,3 +82,33 @@ def test_design_on_coarse_upsampled_grid(setup):
     assert tuple(h.shape) == (nc, nc)
     assert all(np.isfinite(losses))
     assert losses[-1] < 0.7 * losses[0]
+
+
+def test_design_resume_is_bitwise(setup, tmp_path):
+    """Checkpoint / resume on the library path: 3 steps, a checkpoint, a
+    fresh loop resumed from it for 3 more, against 6 uninterrupted steps."""
+    api = setup[0]
+    from paper_2505_22313_amd.design import design_loop
+    n, m = 256, 512
+    lams = np.array([0.45, 0.55, 0.65])
+    prob = api.Problem(n, m, 1.0, 20000.0, lams, wl.cauchy_index(lams))
+    h0 = torch.from_numpy(wl.uniform_heights(n, seed=9)).cuda()
+    target = torch.from_numpy(wl.gaussian_target(n, 3.0, total=3.0 * n * n)).cuda()
+    h_ref, l_ref, _ = design_loop(h0, prob, target, steps=6, lr=1e-2)
+    ck = str(tmp_path / "design.pt")
+
+    calls = {"n": 0}
+
+    def stop_after_3(h, p, a):
+        if calls["n"] == 3:
+            raise KeyboardInterrupt
+        calls["n"] += 1
+        return api.DopPSF.apply(h, p, a)
+
+    with pytest.raises(KeyboardInterrupt):
+        design_loop(h0, prob, target, steps=6, lr=1e-2, psf_fn=stop_after_3, checkpoint=ck,
+                    checkpoint_every=1)
+    h, losses, _ = design_loop(h0, prob, target, steps=6, lr=1e-2, checkpoint=ck,
+                               checkpoint_every=1, resume=True)
+    assert torch.equal(h, h_ref)
+    assert losses == l_ref

@@ -365,7 +365,7 @@ dop_status dop_serve_submit(dop_server *srv, const dop_problem *prob,
 /* Scheduling policies.
  *   DOP_SERVE_CHUNKED (default): a request runs in chunks of one wavelength
  *     group (up to four wavelengths; its workspace holds that many fields,
- *     at most half the arena, or one field when no more fits at admission).
+ *     at most half the arena, or as many fields as fit at admission).
  *     All chunks go through one in-order stream, two enqueued at a time
  *     (up to eight while those hold under 1e8 padded pixels x wavelengths,
  *     about a millisecond of work); each time a chunk completes, the next

@@ -348,7 +348,7 @@ struct dop_server {
     const bool ch = policy == DOP_SERVE_CHUNKED;
     // whole-request policies run one wavelength at a time in one field; the
     // chunked policy gives a request up to a wavelength group of fields, at
-    // most half the arena, or one field if that is all that fits now
+    // most half the arena, or as many fields as fit now (at least one)
     int g = 1;
     if (ch) {
       g = psf_group(&r->prob, nullptr, (size_t)-1);
@@ -357,7 +357,7 @@ struct dop_server {
     size_t off = 0;
     while (!arena.alloc((size_t)g * r->field, &off)) {
       if (g == 1) return false;
-      g = 1;
+      --g;
     }
     r->group = g;
     r->need = (size_t)g * r->field;

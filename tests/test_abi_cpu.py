@@ -447,12 +447,17 @@ def test_serve_chunked_age_bound_zero_is_oldest_first():
     srv = api.Server(1 << 30, max_slots=4, mock_us_per_mpix=1500.0, policy="chunked",
                      age_bound_s=0.0)
     try:
+        t_big = time.perf_counter()
         big = srv.submit(req(2048, 8), 256, 512)     # ~50 ms
         time.sleep(0.005)
+        t_small = time.perf_counter()
         small = srv.submit(req(512), 256, 512)
         for t in (big, small):
             assert srv.wait(t, 10.0) == L.DOP_OK
-        assert srv.latency_ms(small) + 5.0 > srv.latency_ms(big)
+        # completion times (submission + latency): the small one completes last
+        done_big = t_big + srv.latency_ms(big) * 1e-3
+        done_small = t_small + srv.latency_ms(small) * 1e-3
+        assert done_small > done_big - 1e-3
     finally:
         srv.close()
 
@@ -479,6 +484,22 @@ def test_serve_chunked_groups_use_at_most_half_the_arena():
         t = srv.submit(req(1024, 8), 256, 512)   # four fields would not fit half the arena
         assert srv.wait(t, 10.0) == L.DOP_OK
         assert srv.stats()["arena_peak"] == ws(1024)
+    finally:
+        srv.close()
+
+
+def test_serve_chunked_group_shrinks_to_what_fits():
+    """A request whose full group does not fit beside the running ones gets
+    the largest group that does (two fields here), not a single field."""
+    # grids above 2048 (smaller ones run the three-pass path, one field)
+    arena = ws(8192) + ws(4096) * 5 // 2
+    srv = api.Server(arena, max_slots=2, mock_us_per_mpix=200.0, policy="chunked")
+    try:
+        a = srv.submit(req(8192), 256, 512)      # about 4 fields of 4096^2, ~13 ms
+        b = srv.submit(req(4096, 8), 256, 512)   # half the arena allows 3; 2 fit beside a
+        for t in (a, b):
+            assert srv.wait(t, 10.0) == L.DOP_OK
+        assert srv.stats()["arena_peak"] == ws(8192) + 2 * ws(4096)
     finally:
         srv.close()
 

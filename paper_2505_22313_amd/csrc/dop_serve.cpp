@@ -16,9 +16,11 @@
 //    have waited longer than the age bound: then the oldest of those goes
 //    first.  A request that arrives while a large one runs waits for the
 //    chunks already enqueued instead of the whole large request, and the
-//    large one is never slowed by sharing the GPU: it only pauses.  Admission takes the head of the queue first; a request
-//    behind a head that does not fit yet may go ahead of it unless the head
-//    has passed the age bound.
+//    large one is never slowed by sharing the GPU: it only pauses.
+//    Admission takes the head of the queue first; a request behind a head
+//    that does not fit yet may go ahead of it unless the head has passed the
+//    age bound.  An admitted request gets a workspace of up to one group of
+//    fields, at most half the arena, and as many as fit at admission.
 //  - DOP_SERVE_FIFO and DOP_SERVE_SIZE_AWARE: a request's whole PSF is
 //    enqueued at admission on the stream of its slot, so admitted requests
 //    run side by side (processor sharing); admission is strictly in order.

@@ -808,8 +808,14 @@ struct Plan {
   static constexpr int TA = TP.ta ? TP.ta : round64(cmin(1024, cmax(64, AX * RA / (POW2 ? 16 : 8))));
   static constexpr int TB = TP.tb ? TP.tb : !POW2 ? round64(cmin(1024, cmax(64, BX * AY / 8)))
                             : BX * AY > 8192 ? 1024 : threads_for(BX * AY);
+  // pass-C threads: about 16 points each, except 8 on the 2048, 4096 and
+  // 32768 grids, whose 64-, 64- and 256-row transforms spilled registers at
+  // 16 (pass C at 4096^2: 71 -> 53 us per wavelength; at 32768^2: 3.84 ->
+  // 3.69 ms)
   static constexpr int TC = TP.tc ? TP.tc : !POW2 ? round64(cmin(1024, cmax(64, BY * RC / 8)))
-                            : BY * RC > 8192 ? 1024 : threads_for(BY * RC);
+                            : BY * RC > 8192 ? 1024
+                            : (PID == 11 || PID == 12 || PID == 15) ? 2 * threads_for(BY * RC)
+                                                                     : threads_for(BY * RC);
   // Twiddles in LDS: omega_M^q = HI[q / S] * LO[q % S] with HI[i] = omega_M^(i S)
   // (= omega_THI^i) and LO[i] = omega_M^i.  Power-of-two M: THI = min(M, 1024),
   // which also serves every inner DFT length.  Table grids: THI = AX (S = BX),

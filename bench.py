@@ -143,27 +143,40 @@ def serve_measure(api, wl, torch, count, rate_hz, pool, slots=4, seed=5,
     a time on one stream (the plain path, dop_psf with wavelength groups),
     then through the continuous-batching server under each policy (`slots`
     admitted requests, an arena of 2 * slots of the largest one-field
-    workspaces).  Latency = completion - arrival."""
+    workspaces).  Latency = completion - arrival.  The timing does not read
+    the results (the serve tests check them), so outputs are reused round-robin
+    once a size has more than kOutPerSize requests: a 2000-request trace would
+    otherwise need about 700 GB of PSF buffers."""
     import threading
+    kOutPerSize = 16
     trace = wl.serve_trace(count, rate_hz, seed=seed, sizes=tuple(sorted(pool)))
     reqs = []
     for r in trace:
         prob = api.Problem(r["n"], r["m"], r["dx"], r["z"], r["lams"], r["n_index"])
         reqs.append((r["t"], prob, pool[r["n"]][r["pool"]]))
-    outs = [torch.empty((p.n, p.n), dtype=torch.float32, device="cuda") for _, p, _ in reqs]
+    bufs, outs = {}, []
+    for _, p, _ in reqs:
+        ring = bufs.setdefault(p.n, [])
+        if len(ring) < kOutPerSize:
+            ring.append(torch.empty((p.n, p.n), dtype=torch.float32, device="cuda"))
+            outs.append(ring[-1])
+        else:
+            outs.append(ring[len(outs) % kOutPerSize])
     work = sum(p.k * float(p.m) ** 2 for _, p, _ in reqs) / 1e6
     torch.cuda.synchronize()
 
     # one request at a time, in arrival order
     lat_seq = []
     t0 = time.perf_counter()
-    for (ta, prob, h), o in zip(reqs, outs):
+    for i, ((ta, prob, h), o) in enumerate(zip(reqs, outs)):
         now = time.perf_counter() - t0
         if now < ta:
             time.sleep(ta - now)
         api.psf(h, prob, out=o)
         torch.cuda.synchronize()
         lat_seq.append((time.perf_counter() - t0 - ta) * 1e3)
+        if (i + 1) % 250 == 0:
+            log(f"serving: one at a time, {i + 1} of {count} requests")
     span_seq = time.perf_counter() - t0
     api.default_context().release_workspaces()
     torch.cuda.empty_cache()
@@ -185,6 +198,8 @@ def serve_measure(api, wl, torch, count, rate_hz, pool, slots=4, seed=5,
                 if now < ta:
                     time.sleep(ta - now)
                 tickets[i] = srv.submit(prob, h, o)
+                if (i + 1) % 250 == 0:
+                    log(f"serving: {spec}, {i + 1} of {count} requests submitted")
 
         th = threading.Thread(target=submitter)
         th.start()
@@ -200,7 +215,7 @@ def serve_measure(api, wl, torch, count, rate_hz, pool, slots=4, seed=5,
                 "mpix_lambda_s": round(work / span, 1), "arena_peak_gb": round(peak / 1e9, 2)}
 
     res = {pol: served(pol) for pol in policies}
-    del outs
+    del outs, bufs
     torch.cuda.synchronize()
     return {
         "requests": count, "offered_rate_hz": round(rate_hz, 2), "slots": slots,

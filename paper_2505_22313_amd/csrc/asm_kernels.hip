@@ -807,8 +807,12 @@ struct Plan {
   // (other M: about 8 points per thread, since their mixed-radix stage
   // shapes do not divide evenly among threads and need more registers each)
   static constexpr int TA = TP.ta ? TP.ta : round64(cmin(1024, cmax(64, AX * RA / (POW2 ? 16 : 8))));
+  // pass-B / B' threads: about 16 points each, 8 on the 2048 and 4096 grids
+  // (passes B and B' at 4096^2: 61 -> 58 and 52 -> 48 us per wavelength)
   static constexpr int TB = TP.tb ? TP.tb : !POW2 ? round64(cmin(1024, cmax(64, BX * AY / 8)))
-                            : BX * AY > 8192 ? 1024 : threads_for(BX * AY);
+                            : BX * AY > 8192 ? 1024
+                            : (PID == 11 || PID == 12) ? 2 * threads_for(BX * AY)
+                                                       : threads_for(BX * AY);
   // pass-C threads: about 16 points each, except 8 on the 2048, 4096 and
   // 32768 grids, whose 64-, 64- and 256-row transforms spilled registers at
   // 16 (pass C at 4096^2: 71 -> 53 us per wavelength; at 32768^2: 3.84 ->
